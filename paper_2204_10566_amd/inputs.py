@@ -1,0 +1,324 @@
+"""Seeded synthetic inputs: voxel flag fields, initial velocity fields, inlet
+velocity profiles, relaxation parameters and request traces.
+
+This module holds none of the lattice Boltzmann arithmetic: it produces the
+geometry, the boundary data and the initial macroscopic fields that both the
+GPU library and the FP64 oracle take as inputs, so that the two sides see
+identical inputs.  Everything random is drawn from numpy's PCG64 with an
+explicit seed.
+
+Array conventions (shared with the C ABI):
+  flags[nz, ny, nx] uint8 with 0 fluid, 1 solid, 2 inlet, 3 outlet;
+  velocity fields u[3, nz, ny, nx] (x fastest); x is the axial direction.
+
+The synthetic nozzle stands in for the FDA nozzle of the paper (Sec. 2.2,
+"Cases description"), whose geometry file is not available here: an inlet
+pipe, a conical contraction of 20 degrees total angle, a straight throat and a
+sudden expansion back to the pipe radius.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
+CS = 1.0 / math.sqrt(3.0)  # lattice speed of sound, sqrt(theta0) with theta0 = 1/3
+
+PERIODIC_X, PERIODIC_Y, PERIODIC_Z = 1, 2, 4
+
+
+def tau_from_viscosity(nu: float) -> float:
+    """Lattice relaxation time for a lattice kinematic viscosity (Sec. 2.1,
+    Eq. (5), with delta t = 1 and theta0 = 1/3)."""
+    return 3.0 * nu + 0.5
+
+
+# ---------------------------------------------------------------------------
+# Periodic box with a 3-D Taylor-Green vortex
+# ---------------------------------------------------------------------------
+def periodic_box(nx: int, ny: int | None = None, nz: int | None = None) -> np.ndarray:
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    return np.zeros((nz, ny, nx), dtype=np.uint8)
+
+
+def taylor_green_velocity(nx: int, ny: int, nz: int, u0: float) -> np.ndarray:
+    """u_x = u0 sin(kx x) cos(ky y) cos(kz z), u_y = -u0 cos sin cos, u_z = 0,
+    k = 2 pi / N per axis, at integer cell coordinates."""
+    kx, ky, kz = 2 * math.pi / nx, 2 * math.pi / ny, 2 * math.pi / nz
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = u0 * np.sin(kx * x) * np.cos(ky * y) * np.cos(kz * z)
+    u[1] = -u0 * np.cos(kx * x) * np.sin(ky * y) * np.cos(kz * z)
+    return u
+
+
+def taylor_green_2d_velocity(nx: int, ny: int, u0: float) -> np.ndarray:
+    """z-independent Taylor-Green vortex on an nx x ny x 1 box."""
+    kx, ky = 2 * math.pi / nx, 2 * math.pi / ny
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    u = np.zeros((3, 1, ny, nx))
+    u[0, 0] = u0 * np.sin(kx * x) * np.cos(ky * y)
+    u[1, 0] = -u0 * (kx / ky) * np.cos(kx * x) * np.sin(ky * y)
+    return u
+
+
+# ---------------------------------------------------------------------------
+# Channel between two walls normal to y (periodic in x and z)
+# ---------------------------------------------------------------------------
+def channel_flags(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Solid rows at y = 0 and y = ny - 1; the halfway walls sit at y = 0.5
+    and y = ny - 1.5, so the fluid gap is H = ny - 2."""
+    fl = np.zeros((nz, ny, nx), dtype=np.uint8)
+    fl[:, 0, :] = SOLID
+    fl[:, ny - 1, :] = SOLID
+    return fl
+
+
+def shear_wave_velocity(nx: int, ny: int, nz: int, u0: float) -> np.ndarray:
+    """u_x = u0 sin(pi (y - 0.5) / H) between the walls of channel_flags."""
+    H = ny - 2
+    y = np.arange(ny)
+    prof = u0 * np.sin(math.pi * (y - 0.5) / H)
+    prof[0] = prof[-1] = 0.0
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = prof[None, :, None]
+    return u
+
+
+def inflow_channel(nx: int, ny: int, nz: int, u_mean: float):
+    """Channel with walls normal to y, periodic in z, a plane-Poiseuille
+    velocity inlet at x = 0 and an outlet at x = nx - 1.  Returns
+    (flags, u_in[3,nz,ny,nx], periodic_mask)."""
+    fl = channel_flags(nx, ny, nz)
+    fl[:, 1:ny - 1, 0] = INLET
+    fl[:, 1:ny - 1, nx - 1] = OUTLET
+    H = ny - 2
+    y = np.arange(ny) - 0.5
+    prof = 6.0 * u_mean * (y / H) * (1.0 - y / H)
+    uin = np.zeros((3, nz, ny, nx))
+    uin[0, :, 1:ny - 1, 0] = prof[None, 1:ny - 1]
+    return fl, uin, PERIODIC_Z
+
+
+# ---------------------------------------------------------------------------
+# Synthetic sudden-expansion nozzle
+# ---------------------------------------------------------------------------
+@dataclass
+class Nozzle:
+    """Axisymmetric nozzle on an n x n x length voxel grid, axis along x at
+    the cross-section centre.  Radii and lengths in cells."""
+    n: int = 96
+    length: int = 768
+    R: float = 24.0                 # pipe radius (inlet and outlet pipe)
+    r_throat: float = 8.0
+    inlet_len: float | None = None  # default 4 R
+    throat_len: float | None = None  # default 8 R
+    half_angle_deg: float = 10.0    # 20 degrees total cone angle
+
+    def profile(self) -> np.ndarray:
+        """R(x) at the cell centres x + 0.5."""
+        L_in = 4 * self.R if self.inlet_len is None else self.inlet_len
+        L_th = 8 * self.R if self.throat_len is None else self.throat_len
+        L_cone = (self.R - self.r_throat) / math.tan(math.radians(self.half_angle_deg))
+        xc = np.arange(self.length) + 0.5
+        r = np.full(self.length, self.R)
+        cone = (xc >= L_in) & (xc < L_in + L_cone)
+        r[cone] = self.R - (xc[cone] - L_in) * (self.R - self.r_throat) / L_cone
+        throat = (xc >= L_in + L_cone) & (xc < L_in + L_cone + L_th)
+        r[throat] = self.r_throat
+        return r
+
+    def radius_grid(self) -> np.ndarray:
+        """Distance of each (z, y) cell centre from the axis."""
+        c = self.n / 2.0
+        z, y = np.meshgrid(np.arange(self.n) + 0.5, np.arange(self.n) + 0.5, indexing="ij")
+        return np.sqrt((y - c) ** 2 + (z - c) ** 2)
+
+    def flags(self) -> np.ndarray:
+        rr = self.radius_grid()
+        prof = self.profile()
+        inside = rr[:, :, None] < prof[None, None, :]
+        fl = np.where(inside, FLUID, SOLID).astype(np.uint8)
+        fl[:, :, 0] = np.where(inside[:, :, 0], INLET, SOLID)
+        fl[:, :, -1] = np.where(inside[:, :, -1], OUTLET, SOLID)
+        return fl
+
+    def mean_inlet_velocity(self, u_throat_mean: float) -> float:
+        """u0 = u_thr (d_thr / d0)^2 (Sec. 2.2, Eq. (11))."""
+        return u_throat_mean * (self.r_throat / self.R) ** 2
+
+    def inlet_velocity(self, u_throat_mean: float, noise: float = 0.0, seed: int = 0) -> np.ndarray:
+        """Parabolic inlet profile u(r) = 2 u0 (1 - 4 r^2 / d0^2) (Sec. 2.2,
+        Eq. (12)) on the inlet cells, plus optional frozen uniform noise of
+        relative amplitude `noise` (times u0) on all three components."""
+        u0 = self.mean_inlet_velocity(u_throat_mean)
+        d0 = 2.0 * self.R
+        rr = self.radius_grid()
+        fl = self.flags()
+        uin = np.zeros((3, self.n, self.n, self.length))
+        prof = 2.0 * u0 * (1.0 - 4.0 * rr ** 2 / d0 ** 2)
+        mask = fl[:, :, 0] == INLET
+        uin[0, :, :, 0] = np.where(mask, prof, 0.0)
+        if noise > 0.0:
+            rng = np.random.Generator(np.random.PCG64(seed))
+            pert = rng.uniform(-1.0, 1.0, size=(3, self.n, self.n))
+            for a in range(3):
+                uin[a, :, :, 0] += np.where(mask, noise * u0 * pert[a], 0.0)
+        return uin
+
+    def initial_velocity(self, u_throat_mean: float) -> np.ndarray:
+        """Plug flow u_x = u0 (R / R(x))^2 on fluid cells (mass consistent)."""
+        u0 = self.mean_inlet_velocity(u_throat_mean)
+        fl = self.flags()
+        prof = self.profile()
+        u = np.zeros((3, self.n, self.n, self.length))
+        ux = u0 * (self.R / prof) ** 2
+        u[0] = np.where((fl == FLUID) | (fl == OUTLET), ux[None, None, :], 0.0)
+        return u
+
+
+def nozzle_tau(nz: Nozzle, Re: float, mach: float = 0.1) -> tuple[float, float]:
+    """(tau, mean throat velocity) for a Reynolds number on the throat
+    diameter (Sec. 2.2, Eq. (10)) with the peak throat velocity
+    2 u_thr = mach * c_s."""
+    u_thr = 0.5 * mach * CS
+    nu = u_thr * (2.0 * nz.r_throat) / Re
+    return tau_from_viscosity(nu), u_thr
+
+
+def nozzle_config(which: str = "re500") -> dict:
+    """The two nozzle workloads: 96x96x768 at Re 500 and 128x128x1536 at
+    Re 6500 with 1 % inlet noise."""
+    if which == "re500":
+        nz = Nozzle(n=96, length=768, R=24.0, r_throat=8.0)
+        Re, noise = 500.0, 0.0
+    elif which == "re6500":
+        s = 4.0 / 3.0
+        nz = Nozzle(n=128, length=1536, R=24.0 * s, r_throat=8.0 * s)
+        Re, noise = 6500.0, 0.01
+    else:
+        raise ValueError(which)
+    tau, u_thr = nozzle_tau(nz, Re)
+    return {
+        "nozzle": nz,
+        "flags": nz.flags(),
+        "uin": nz.inlet_velocity(u_thr, noise=noise, seed=0),
+        "u0": nz.initial_velocity(u_thr),
+        "tau": tau,
+        "u_thr": u_thr,
+        "Re": Re,
+        "periodic": 0,
+    }
+
+
+def small_nozzle(n: int = 24, length: int = 160, R: float = 8.0, r_throat: float = 3.0, Re: float = 100.0):
+    """A scaled-down nozzle for tests the oracle can run in full."""
+    nz = Nozzle(n=n, length=length, R=R, r_throat=r_throat, inlet_len=2 * R, throat_len=3 * R)
+    tau, u_thr = nozzle_tau(nz, Re)
+    return {
+        "nozzle": nz,
+        "flags": nz.flags(),
+        "uin": nz.inlet_velocity(u_thr, noise=0.01, seed=1),
+        "u0": nz.initial_velocity(u_thr),
+        "tau": tau,
+        "u_thr": u_thr,
+        "Re": Re,
+        "periodic": 0,
+    }
+
+
+# ---------------------------------------------------------------------------
+# Batched and serving workloads
+# ---------------------------------------------------------------------------
+@dataclass
+class DomainSpec:
+    kind: str                 # "tgv" (periodic box) or "channel"
+    nx: int
+    ny: int
+    nz: int
+    tau: float
+    steps: int
+    u0: float = 0.02
+    periodic: int = PERIODIC_X | PERIODIC_Y | PERIODIC_Z
+    flags: np.ndarray | None = field(default=None, repr=False)
+    u: np.ndarray | None = field(default=None, repr=False)
+    uin: np.ndarray | None = field(default=None, repr=False)
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def materialise(self) -> "DomainSpec":
+        if self.kind == "tgv":
+            self.flags = periodic_box(self.nx, self.ny, self.nz)
+            self.u = taylor_green_velocity(self.nx, self.ny, self.nz, self.u0)
+            self.periodic = PERIODIC_X | PERIODIC_Y | PERIODIC_Z
+        elif self.kind == "channel":
+            self.flags = channel_flags(self.nx, self.ny, self.nz)
+            self.u = shear_wave_velocity(self.nx, self.ny, self.nz, self.u0)
+            self.periodic = PERIODIC_X | PERIODIC_Z
+        else:
+            raise ValueError(self.kind)
+        return self
+
+
+def batched_domains(count: int = 64, seed: int = 0, lo: int = 16, hi: int = 128, steps: int = 500,
+                    materialise: bool = False) -> list[DomainSpec]:
+    """Independent periodic-TGV or channel domains: edge n uniform in
+    {lo..hi}, cube n^3 or 2n x n x n box (coin flip), tau uniform in
+    [0.51, 0.8]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(lo, hi + 1))
+        box = bool(rng.integers(0, 2))
+        kind = "tgv" if rng.integers(0, 2) == 0 else "channel"
+        tau = float(rng.uniform(0.51, 0.8))
+        nx = 2 * n if box else n
+        d = DomainSpec(kind=kind, nx=nx, ny=n, nz=n, tau=tau, steps=steps)
+        out.append(d.materialise() if materialise else d)
+    return out
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float           # seconds after the start of the trace
+    nozzle: Nozzle
+    Re: float
+    steps: int
+
+    def build(self):
+        tau, u_thr = nozzle_tau(self.nozzle, self.Re)
+        return {
+            "flags": self.nozzle.flags(),
+            "uin": self.nozzle.inlet_velocity(u_thr),
+            "u0": self.nozzle.initial_velocity(u_thr),
+            "tau": tau,
+        }
+
+
+def serving_trace(count: int = 200, rate: float = 20.0, seed: int = 0, steps_lo: int = 1000,
+                  steps_hi: int = 5000) -> list[Request]:
+    """Poisson arrivals (mean `rate` per second) of nozzle-like solves:
+    cross-section n in {64, 80, 96, 112, 128}, length k n with k in {4..8},
+    pipe radius n/4, throat/pipe radius ratio uniform in [0.25, 0.5], Re
+    uniform in [500, 6500], step count uniform in {steps_lo..steps_hi}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for rid in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(rng.choice([64, 80, 96, 112, 128]))
+        k = int(rng.integers(4, 9))
+        R = n / 4.0
+        ratio = float(rng.uniform(0.25, 0.5))
+        Re = float(rng.uniform(500.0, 6500.0))
+        steps = int(rng.integers(steps_lo, steps_hi + 1))
+        nz = Nozzle(n=n, length=k * n, R=R, r_throat=R * ratio, inlet_len=2 * R,
+                    throat_len=min(8 * R, k * n / 4.0))
+        out.append(Request(rid=rid, arrival=t, nozzle=nz, Re=Re, steps=steps))
+    return out

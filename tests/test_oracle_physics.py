@@ -1,0 +1,227 @@
+"""Pins of the oracle's streaming, boundary treatment and dynamics.
+
+Exact pins: pure advection equals np.roll on a periodic box; halfway
+bounce-back is a permutation that returns a channel state after 2W steps;
+mass and momentum are conserved to round-off.  Physical pins with a stated
+tolerance: viscous decay of a Taylor-Green vortex and of a wall-bounded shear
+wave at nu = theta0 (tau - 1/2) (Sec. 2.1, Eq. (5)); a velocity-inlet /
+zero-gradient outlet passing a uniform stream unchanged, and the inlet
+injecting exactly its prescribed mass flux (Sec. 2.2, "Simulation details")."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2204_10566_amd import inputs as I
+
+THETA0 = 1.0 / 3.0
+C = np.array([(i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1) for i in range(27)])
+
+
+def random_field(orc, shape, seed, amp=0.02):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    rho = 1 + 0.01 * rng.uniform(-1, 1, shape)
+    u = 0.03 * rng.uniform(-1, 1, (3,) + shape)
+    f = orc.init_fields(np.zeros(shape, np.uint8), rho, u)
+    return f * (1 + amp * rng.uniform(-1, 1, f.shape))
+
+
+def test_pure_advection_is_roll(orc):
+    """All rates 0: the collision is the identity and one step moves
+    population i by c_i (pull form of the streaming term of Eq. (3))."""
+    shape = (5, 6, 7)
+    f = random_field(orc, shape, 0)
+    st, g = orc.step(np.zeros(shape, np.uint8), f, orc.rates_vector(0.0, 0.0, 0.0), 1, periodic=7)
+    assert st == 0
+    for i in range(27):
+        ref = np.roll(f[i], shift=(C[i, 2], C[i, 1], C[i, 0]), axis=(0, 1, 2))
+        assert np.array_equal(g[i], ref)
+
+
+def test_pure_advection_returns_after_period(orc):
+    n = 6
+    f = random_field(orc, (n, n, n), 1)
+    st, g = orc.step(np.zeros((n, n, n), np.uint8), f, orc.rates_vector(0.0, 0.0, 0.0), n, periodic=7)
+    assert np.array_equal(g, f)
+
+
+def test_halfway_bounce_back_round_trip(orc):
+    """Walls at x = 0 and x = W + 1, periodic y and z of length W: with no
+    collision every population returns after 2W steps (halfway bounce-back
+    reverses a population within one step at the wall)."""
+    W = 4
+    fl = np.zeros((W, W, W + 2), np.uint8)
+    fl[:, :, 0] = fl[:, :, -1] = I.SOLID
+    f = random_field(orc, fl.shape, 2)
+    f[:, fl == I.SOLID] = 0
+    st, g = orc.step(fl, f, orc.rates_vector(0.0, 0.0, 0.0), 2 * W, periodic=6)
+    assert np.array_equal(g[:, fl == 0], f[:, fl == 0])
+    st, g1 = orc.step(fl, f, orc.rates_vector(0.0, 0.0, 0.0), 1, periodic=6)
+    # a population leaving the first fluid cell toward the wall comes back
+    # reversed in the same cell after one step
+    i_in = 13 + 1   # c = (+1, 0, 0)
+    i_out = 13 - 1  # c = (-1, 0, 0)
+    assert np.array_equal(g1[i_in][:, :, 1], f[i_out][:, :, 1])
+
+
+def test_periodic_conservation(orc):
+    shape = (8, 8, 8)
+    f = random_field(orc, shape, 3, amp=0.05)
+    fl = np.zeros(shape, np.uint8)
+    st, g = orc.step(fl, f, orc.rates_vector(1 / 0.52, 1.1, 1.0), 60, periodic=7)
+    assert st == 0
+    assert abs(g.sum() - f.sum()) / f.sum() < 1e-13
+    for a in range(3):
+        j0 = np.tensordot(C[:, a], f, axes=(0, 0)).sum()
+        j1 = np.tensordot(C[:, a], g, axes=(0, 0)).sum()
+        assert abs(j1 - j0) < 1e-12
+
+
+def test_closed_box_conserves_mass(orc):
+    fl = np.ones((6, 7, 8), np.uint8)
+    fl[1:-1, 1:-1, 1:-1] = 0
+    f = random_field(orc, fl.shape, 4, amp=0.05)
+    f[:, fl == 1] = 0
+    st, g = orc.step(fl, f, orc.rates_vector(1 / 0.6, 1.0, 1.0), 50, periodic=0)
+    assert st == 0
+    assert abs(g.sum() - f.sum()) / f.sum() < 1e-13
+
+
+def decay_rate(series, t):
+    return -np.polyfit(t, np.log(series), 1)[0]
+
+
+def test_taylor_green_2d_viscous_decay(orc):
+    """2-D Taylor-Green vortex amplitude decays as exp(-nu (kx^2 + ky^2) t)
+    with nu = theta0 (tau - 1/2); tolerance 0.5 %."""
+    n, tau, u0 = 32, 0.6, 0.01
+    fl = np.zeros((1, n, n), np.uint8)
+    u = I.taylor_green_2d_velocity(n, n, u0)
+    f = orc.init_fields(fl, None, u)
+    rates = orc.rates_vector(1 / tau, 1 / tau, 1.0)
+    mode = np.sin(2 * math.pi * np.arange(n) / n)[None, :] * np.cos(2 * math.pi * np.arange(n) / n)[:, None]
+    amps, ts = [], []
+    for t in range(0, 161, 20):
+        if t:
+            st, f = orc.step(fl, f, rates, 20, periodic=7)
+            assert st == 0
+        _, uu = orc.moments(fl, f)
+        if t >= 20:
+            amps.append((uu[0, 0] * mode).sum() / (mode * mode).sum())
+            ts.append(t)
+    nu = THETA0 * (tau - 0.5)
+    k2 = 2 * (2 * math.pi / n) ** 2
+    assert abs(decay_rate(amps, ts) / (nu * k2) - 1) < 5e-3
+
+
+def test_shear_wave_between_walls(orc):
+    """u_x = u0 sin(pi (y - 1/2) / H) between halfway bounce-back walls decays
+    at nu (pi / H)^2; tolerance 0.5 % at H = 16."""
+    H, tau = 16, 0.6
+    fl = I.channel_flags(1, H + 2, 1)
+    u = I.shear_wave_velocity(1, H + 2, 1, 0.01)
+    f = orc.init_fields(fl, None, u)
+    rates = orc.rates_vector(1 / tau, 1 / tau, 1.0)
+    prof = np.sin(math.pi * (np.arange(H + 2) - 0.5) / H)
+    prof[0] = prof[-1] = 0
+    amps, ts = [], []
+    for t in range(0, 801, 100):
+        if t:
+            st, f = orc.step(fl, f, rates, 100, periodic=5)
+        _, uu = orc.moments(fl, f)
+        if t >= 100:
+            amps.append((uu[0, 0, :, 0] * prof).sum() / (prof * prof).sum())
+            ts.append(t)
+    nu = THETA0 * (tau - 0.5)
+    assert abs(decay_rate(amps, ts) / (nu * (math.pi / H) ** 2) - 1) < 5e-3
+
+
+def plug_box(nx, ny, nz):
+    fl = np.zeros((nz, ny, nx), np.uint8)
+    fl[:, :, 0] = I.INLET
+    fl[:, :, -1] = I.OUTLET
+    return fl
+
+
+def test_plug_flow_is_fixed_point_of_inlet_and_outlet(orc):
+    """A uniform stream f^eq(1, u_in) through a periodic-y/z box with the
+    moving-wall inlet and the zero-gradient outlet is stationary: the inlet
+    term 2 w_i (c_i . u_in) / theta0 restores exactly the equilibrium
+    difference f^eq_i - f^eq_(opposite i), and the outlet copies it."""
+    nx, ny, nz, u0 = 12, 3, 2, 0.03
+    fl = plug_box(nx, ny, nz)
+    uin = np.zeros((3, nz, ny, nx))
+    uin[0, :, :, 0] = u0
+    u = np.zeros((3, nz, ny, nx))
+    u[0][fl != I.INLET] = u0
+    f = orc.init_fields(fl, None, u)
+    st, g = orc.step(fl, f, orc.rates_vector(1 / 0.7, 1.2, 1.0), 50, periodic=6, uin=uin)
+    upd = fl != I.INLET
+    assert st == 0 and np.abs(g[:, upd] - f[:, upd]).max() < 1e-15
+
+
+def test_plug_flow_develops_from_rest(orc):
+    nx, ny, nz, u0 = 20, 2, 2, 0.02
+    fl = plug_box(nx, ny, nz)
+    uin = np.zeros((3, nz, ny, nx))
+    uin[0, :, :, 0] = u0
+    f = orc.init_fields(fl, None, None)
+    st, f = orc.step(fl, f, orc.rates_vector(1.0, 1.0, 1.0), 800, periodic=6, uin=uin)
+    rho, u = orc.moments(fl, f)
+    j = (rho * u[0])[:, :, 1:]
+    assert st == 0 and np.abs(j / u0 - 1).max() < 1e-3
+    assert np.abs(u[1:, :, :, 1:]).max() < 1e-6
+
+
+def test_inlet_injects_exact_mass_flux(orc):
+    """With the outlet closed, the only change of total mass is the inlet's
+    moving-wall term: per step, the sum over every inlet link into a fluid
+    cell of 2 w_i rho_w (c_i . u_in) / theta0 with rho_w = 1 (Sec. 2.2,
+    Eq. (12) profile on the inlet cells)."""
+    nx, H = 10, 6
+    fl, uin, per = I.inflow_channel(nx, H + 2, 3, 0.02)
+    fl[fl == I.OUTLET] = I.SOLID
+    rng = np.random.default_rng(7)
+    uin[:, fl == I.INLET] += 0.003 * rng.uniform(-1, 1, (3, int((fl == I.INLET).sum())))
+    _, w = orc.velocity_set()
+    nz, ny, _ = fl.shape
+    expect = 0.0
+    for z, y in zip(*np.nonzero(fl[:, :, 0] == I.INLET)):
+        for i in range(27):
+            if C[i, 0] != 1:
+                continue
+            tz, ty = (z + C[i, 2]) % nz, y + C[i, 1]
+            if 0 <= ty < ny and fl[tz, ty, 1] == I.FLUID:
+                expect += 3.0 * 2.0 * w[i] * (C[i] @ uin[:, z, y, 0])
+    f = orc.init_fields(fl, None, None)
+    upd = fl == I.FLUID
+    m0 = f[:, upd].sum()
+    for s in range(1, 4):
+        st, f = orc.step(fl, f, orc.rates_vector(1 / 0.8, 1.0, 1.0), 1, periodic=per, uin=uin)
+        assert abs(f[:, upd].sum() - m0 - s * expect) < 1e-12
+
+
+def test_unstable_state_reported(orc):
+    """A negative-density state is reported as unstable, not hidden."""
+    fl = np.zeros((2, 2, 2), np.uint8)
+    f = -orc.init_fields(fl, None, None)
+    st, _ = orc.step(fl, f, orc.rates_vector(1.5, 1.5, 1.0), 1, periodic=7)
+    assert st == orc.ERR_UNSTABLE
+
+
+def test_run_cells_matches_full_step(orc):
+    """The sampled (dependency-cone) run equals the full-field run at the
+    listed cells, on a small nozzle with inlet, walls and outlet."""
+    cfg = I.small_nozzle(n=12, length=40, R=5.0, r_throat=2.5)
+    fl = cfg["flags"]
+    rates = orc.rates_vector(1 / cfg["tau"], 1 / cfg["tau"], 1.0)
+    f0 = orc.init_fields(fl, None, cfg["u0"])
+    st, f = orc.step(fl, f0, rates, 3, periodic=0, uin=cfg["uin"])
+    assert st == 0
+    upd = np.flatnonzero((fl.ravel() == 0) | (fl.ravel() == 3))
+    rng = np.random.default_rng(0)
+    cells = np.concatenate([upd[:5], upd[-5:], rng.choice(upd, 30, replace=False)])
+    st, fc = orc.run_cells(fl, cells, rates, 3, periodic=0, uin=cfg["uin"], u0=cfg["u0"])
+    assert st == 0
+    assert np.array_equal(fc, f.reshape(27, -1)[:, cells])
