@@ -1,0 +1,188 @@
+"""Benchmark of the fused D3Q27 CHM-MRT stream-collide step on one MI355X.
+
+Workload: the synthetic sudden-expansion nozzle on a 96 x 96 x 768 voxel grid
+(x axial; inlet pipe radius 24, 20-degree cone to a throat of radius 8, throat
+8 R long, sudden expansion back to R), Re 500 on the throat diameter,
+Ma <= 0.1, halfway bounce-back walls, Poiseuille velocity inlet,
+zero-gradient outlet, FP32 populations.  A step is one lbm_step: the whole
+fused update of every fluid cell (pull gather with boundary resolution,
+moments, forward central-Hermite transform, relaxation, inverse transform,
+store), replayed from a captured HIP graph.
+
+Prints one JSON line.  value = fluid-cell MLUPS over the timed steps, with
+all state resident in HBM.  roofline.achieved = algorithmic bytes per launch
+(216 B per updated cell for FP32: 27 loads + 27 stores) / average launch
+duration, timed with HIP events on the library's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "MLUPS + % peak HBM BW (D3Q27 CHM); batched p50/p99 latency vs serial"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def read_traffic(kernel: str, storage: str):
+    """HBM traffic per launch measured with rocprofv3 counters, from the
+    committed summary (None when absent)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{storage}.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":", 1)[1])
+    return None
+
+
+def time_steps(capi, torch, cfg, storage, steps, warmup, stream):
+    d = capi.Domain(cfg["flags"], periodic=cfg["periodic"], storage=storage, stream=stream.cuda_stream)
+    d.set_params(cfg["tau"], 1.0 / cfg["tau"], 1.0)
+    d.set_inlet(cfg["uin"])
+    d.init_fields(None, cfg["u0"])
+    info = d.info()
+    if warmup:
+        d.step(warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    rc = d.step_status(steps)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rho, u = d.moments()
+    d.destroy()
+    return info, ms, rc, rho, u
+
+
+def cpu_baseline(cfg, nsteps=3):
+    import numpy as np
+
+    import oracle
+
+    fl = cfg["flags"]
+    t0 = time.perf_counter()
+    f = oracle.init_fields(fl, None, cfg["u0"])
+    t1 = time.perf_counter()
+    st, f = oracle.step(fl, f, oracle.rates_vector(1.0 / cfg["tau"]), nsteps, periodic=cfg["periodic"],
+                        uin=cfg["uin"])
+    t2 = time.perf_counter()
+    n_upd = int(((fl == 0) | (fl == 3)).sum())
+    return {
+        "value": round(n_upd * nsteps / (t2 - t1) / 1e6, 4),
+        "unit": "MLUPS",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": f"{nsteps} FP64 oracle steps (dense 27x27 transform + Gaussian elimination per cell) of the "
+                  f"full 96x96x768 nozzle ({n_upd} updated cells) from the plug-flow start; "
+                  f"{t2 - t1:.1f} s stepping, {t1 - t0:.1f} s equilibrium init not counted",
+        "status": int(st),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16s", "bf16s"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path: "
+              "the single-domain update runs on one MI355X and independent requests would be sharded per GPU.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2204_10566_amd import capi
+    from paper_2204_10566_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    cfg = I.nozzle_config("re500")
+    for k in ("uin", "u0"):
+        cfg[k] = cfg[k].astype(np.float32)
+    log(f"nozzle 96x96x768 re500 tau={cfg['tau']:.6f} storage={args.storage} steps={args.steps} "
+        f"warmup={args.warmup}")
+    info, ms, rc, rho, u = time_steps(capi, torch, cfg, args.storage, args.steps, args.warmup, stream)
+    n_upd = int(info.n_updated)
+    ms_step = ms / args.steps
+    mlups = n_upd * args.steps / (ms * 1e-3) / 1e6
+    all_mlups = info.ncells * args.steps / (ms * 1e-3) / 1e6
+    bpc = int(info.bytes_per_cell_update)
+    achieved = n_upd * bpc / (ms_step * 1e-3) / 1e9
+    log(f"{args.storage}: {ms_step * 1e3:.2f} us/step, {mlups:.0f} fluid MLUPS, {achieved:.0f} GB/s algorithmic, "
+        f"status {rc}")
+    traffic = read_traffic("stream_collide", args.storage)
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "fp32" else f"f32 compute, {args.storage} storage",
+        "data": "synthetic",
+        "config": {
+            "workload": "synthetic sudden-expansion nozzle 96x96x768 (x axial), Re 500, FP32 populations, "
+                        "halfway bounce-back, Poiseuille velocity inlet, zero-gradient outlet",
+            "cells": int(info.ncells),
+            "fluid_cells": n_upd,
+            "tiles": int(info.n_tiles),
+            "wall_tiles": int(info.n_wall_tiles),
+            "tau": round(cfg["tau"], 8),
+            "storage": args.storage,
+            "all_cell_mlups": round(all_mlups, 2),
+            "status": int(rc),
+            "max_abs_u": float(np.abs(u).max()),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 2),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_fluid_cell": bpc,
+        },
+    }
+    if not args.no_variants and args.storage == "fp32":
+        var = {}
+        for st in ("fp16s", "bf16s"):
+            vsteps = max(200, args.steps // 4)
+            vinfo, vms, vrc, _, _ = time_steps(capi, torch, cfg, st, vsteps, args.warmup, stream)
+            v = n_upd * vsteps / (vms * 1e-3) / 1e6
+            var[st] = {"mlups": round(v, 2), "ratio_vs_fp32": round(v / mlups, 3),
+                       "achieved_gbs": round(n_upd * vinfo.bytes_per_cell_update / (vms / vsteps * 1e-3) / 1e9, 1),
+                       "steps": vsteps, "status": int(vrc)}
+            log(f"{st}: {v:.0f} fluid MLUPS ({v / mlups:.2f}x fp32)")
+        out["variants"] = var
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle)")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,256 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D3Q27 central-Hermite-moment MRT
+ * lattice Boltzmann library.
+ *
+ * The library advances the scheme of Huang, Noel, Berg and Hosseini,
+ * "Simulation of the FDA Nozzle Benchmark: A Lattice Boltzmann Study":
+ * the update of Sec. 2.1, Eq. (6), with the central Hermite moments of
+ * Eqs. (7)-(8), the full (sixth-order) Hermite equilibrium of Eq. (4) and
+ * App. A, Eqs. (A.4)-(A.6), relaxation rates as stated after Eq. (8) and in
+ * App. A, on the D3Q27 stencil of App. A, Eqs. (A.1)-(A.2); streaming in
+ * pull form; halfway bounce-back walls, a moving-wall velocity inlet
+ * (profile of Sec. 2.2, Eq. (12)) and a zero-gradient outlet.  Every step of
+ * the update runs in the library's own HIP kernels.
+ *
+ * Conventions
+ *   - Every function returns an int status: LBM_OK (0) or a negative
+ *     lbm_status code; none aborts or exits.  lbm_last_error() returns a
+ *     thread-local message for the last failing call on that thread.
+ *   - A NULL domain or batch handle returns LBM_ERR_ARG.
+ *   - Host arrays passed in are owned by the caller and are only read or
+ *     written during the call.  Device memory the library allocates is
+ *     owned by the library and freed by lbm_destroy / lbm_batch_destroy.
+ *   - Grid layout: cell = (z*ny + y)*nx + x, x fastest and contiguous.  x is
+ *     the axial (inlet-to-outlet) direction.
+ *   - Population order: i = (cx+1) + 3(cy+1) + 9(cz+1) for the velocity
+ *     c_i = (cx, cy, cz) in {-1,0,1}^3; the opposite of i is 26 - i.
+ *   - Populations are stored structure-of-arrays, f[i*P + cell], with a
+ *     plane stride P = ncells rounded up to a multiple of 64.
+ *   - The stored state is the post-collision population of the last step.
+ *   - Calls on one domain are not thread-safe; different domains may be
+ *     used from different threads.  All work is issued on the domain's
+ *     stream; the calls below return only after that work completed.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_Q 27
+
+/* Voxel flags (one uint8 per cell). */
+enum lbm_flag {
+    LBM_FLUID = 0,  /* updated every step */
+    LBM_SOLID = 1,  /* wall: links into it are halfway bounce-back */
+    LBM_INLET = 2,  /* moving wall carrying the inlet velocity; never updated */
+    LBM_OUTLET = 3  /* fluid cell on the last x plane with a zero-gradient
+                       outlet: sources beyond x = nx-1 are taken from
+                       x = nx-1 (same y, z shift); updated every step */
+};
+
+/* Population storage. */
+enum lbm_storage {
+    LBM_FP32 = 0,  /* f_i as FP32 */
+    LBM_FP16S = 1, /* 2^14 * (f_i - w_i) as IEEE FP16, rounded to nearest even */
+    LBM_BF16S = 2  /* (f_i - w_i) as bfloat16, rounded to nearest even */
+};
+
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_ERR_ARG = -1,      /* invalid argument; nothing changed */
+    LBM_ERR_OOM = -2,      /* device allocation failed, or a batch budget is exceeded */
+    LBM_ERR_DEVICE = -3,   /* a HIP runtime call failed */
+    LBM_ERR_UNSTABLE = -4, /* a step produced rho <= 0 or a non-finite value */
+    LBM_ERR_STATE = -5     /* call not valid in the current state */
+};
+
+/* Periodicity bits. */
+#define LBM_PERIODIC_X 1u
+#define LBM_PERIODIC_Y 2u
+#define LBM_PERIODIC_Z 4u
+
+typedef struct lbm_domain lbm_domain;
+typedef struct lbm_batch lbm_batch;
+
+typedef struct lbm_domain_info {
+    int nx, ny, nz;
+    int storage;
+    unsigned periodic;
+    uint64_t ncells;        /* nx*ny*nz */
+    uint64_t plane_stride;  /* P */
+    uint64_t n_updated;     /* fluid + outlet cells: the cells one step updates */
+    uint64_t n_tiles;       /* 64-cell tiles holding at least one updated cell */
+    uint64_t n_wall_tiles;  /* of those, tiles with a non-plain link or a non-updated cell */
+    uint64_t device_bytes;  /* device memory held by the domain */
+    uint64_t bytes_per_cell_update; /* algorithmic HBM bytes per updated cell: 2*27*sizeof(storage) */
+} lbm_domain_info;
+
+/*
+ * Create a domain from a voxel flag field (the geometry input of Sec. 2.2).
+ *   flags        host, nx*ny*nz uint8 (enum lbm_flag), read during the call.
+ *                LBM_OUTLET is only valid on the plane x = nx-1 with x not
+ *                periodic.  Non-periodic box faces act as walls.
+ *   periodic     LBM_PERIODIC_* bits.
+ *   storage      enum lbm_storage.
+ *   hip_stream   hipStream_t to issue work on, or NULL for a stream the
+ *                library creates.  The stream must outlive the domain.
+ * Allocates both population buffers and initialises f = f^eq(1, 0).
+ * A domain needs 27*P*sizeof(storage) < 4 GiB.
+ * Errors: LBM_ERR_ARG (bad sizes, flags or storage), LBM_ERR_OOM,
+ * LBM_ERR_DEVICE.
+ */
+int lbm_create_domain(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
+                      void *hip_stream, lbm_domain **out);
+
+/*
+ * As lbm_create_domain, but adopts two caller-allocated device buffers of
+ * 27*P elements each (sizeof(storage) bytes per element, 256-byte aligned),
+ * e.g. from torch.  The caller keeps ownership; the buffers must outlive
+ * the domain.  P is ncells rounded up to a multiple of 64.
+ */
+int lbm_create_domain_ext(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
+                          void *hip_stream, void *f_a, void *f_b, lbm_domain **out);
+
+/*
+ * Relaxation parameters (Sec. 2.1, Eq. (5) and the text after Eq. (8);
+ * App. A after Eq. (A.6)).
+ *   tau         lattice relaxation time, > 0.5; the shear rate is 1/tau and
+ *               relaxes the deviatoric and off-diagonal second-order
+ *               central moments (nu = (tau - 1/2)/3).
+ *   omega_bulk  rate of the trace of the second-order central moments, in
+ *               (0, 2); the paper's choice is 1/tau.
+ *   omega_high  rate of every central moment of order >= 3, in (0, 2]; the
+ *               paper's choice is 1.
+ * Errors: LBM_ERR_ARG when out of range.
+ */
+int lbm_set_params(lbm_domain *d, double tau, double omega_bulk, double omega_high);
+
+/* As lbm_set_params with the shear rate given directly; every rate may be
+ * anywhere in [0, 2] (0 leaves that group of moments unrelaxed; all zero
+ * is pure streaming).  For tests and stability studies. */
+int lbm_set_rates(lbm_domain *d, double omega, double omega_bulk, double omega_high);
+
+/*
+ * Inlet velocity (Sec. 2.2, Eq. (12) profile, or any field).
+ *   u_in  host, 3*ncells floats, layout [component][cell]; read only at
+ *         LBM_INLET cells.  A link from an inlet cell s into a fluid cell x
+ *         gives f_i(x) = f*_opp(i)(x) + 6 w_i (c_i . u_in(s)) (wall density 1).
+ * Without a call, inlet cells act as resting walls.
+ */
+int lbm_set_inlet(lbm_domain *d, const float *u_in);
+
+/*
+ * Set the state to the equilibrium f^eq(rho, u) (Eq. (4), sixth order) at
+ * every updated cell.
+ *   rho  host, ncells floats, or NULL for 1.
+ *   u    host, 3*ncells floats [component][cell], or NULL for 0.
+ * Clears a sticky LBM_ERR_UNSTABLE.
+ */
+int lbm_init_fields(lbm_domain *d, const float *rho, const float *u);
+
+/*
+ * Advance n >= 0 time steps (each: pull streaming with the boundary rules,
+ * then the CHM-MRT collision of Eq. (6), fused in one kernel per step).
+ * Synchronous.  Returns LBM_ERR_UNSTABLE if any step produced rho <= 0 or
+ * a non-finite value; the error is sticky until lbm_init_fields.
+ */
+int lbm_step(lbm_domain *d, int n);
+
+/*
+ * Density and velocity of the stored state (equal to the pre-collision
+ * moments of the same time level, since collision conserves them).
+ *   rho  host, ncells floats; u host, 3*ncells floats [component][cell].
+ * Cells that are not updated read rho = 0, u = 0.
+ */
+int lbm_get_moments(lbm_domain *d, float *rho, float *u);
+
+/* As lbm_get_moments, into device buffers (ncells and 3*ncells floats). */
+int lbm_get_moments_device(lbm_domain *d, float *rho_dev, float *u_dev);
+
+/*
+ * The stored populations f_i as FP32 (shifted storage is converted back:
+ * f_i = w_i + stored/scale).
+ *   f  host, 27*ncells floats, layout [i][cell].
+ * Values at cells that are not updated are unspecified.
+ */
+int lbm_get_populations(lbm_domain *d, float *f);
+
+/* Overwrite the stored populations (FP32 values of f_i, [i][cell], host);
+ * converted to the domain's storage. */
+int lbm_set_populations(lbm_domain *d, const float *f);
+
+int lbm_domain_get_info(const lbm_domain *d, lbm_domain_info *info);
+
+/* Free the domain's device memory and its captured graphs.  A domain
+ * resident in a batch must be released from it first (LBM_ERR_STATE). */
+int lbm_destroy(lbm_domain *d);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *lbm_last_error(void);
+
+/* -------------------------------------------------------------------- */
+/* Batched execution: many independent domains advanced by one packed    */
+/* launch per time step, replayed from a captured HIP graph.            */
+/* -------------------------------------------------------------------- */
+
+/*
+ * Create a batch.
+ *   hbm_budget_bytes  admission limit on the sum of the resident domains'
+ *                     device_bytes.
+ *   storage           every admitted domain must use this storage.
+ *   hip_stream        stream for the batch's work, or NULL for an own one.
+ */
+int lbm_batch_create(size_t hbm_budget_bytes, int storage, void *hip_stream, lbm_batch **out);
+
+/*
+ * Admit a domain for n_steps > 0 further steps, starting at the batch's next
+ * step.  The domain's state stays where it is (no copy).  The call does not
+ * wait for work in flight.  Returns LBM_ERR_OOM when the domain does not fit
+ * the remaining budget (the caller keeps it queued), LBM_ERR_STATE if the
+ * domain is already resident.  *slot receives the slot id.
+ */
+int lbm_batch_admit(lbm_batch *b, lbm_domain *d, int n_steps, int *slot);
+
+/* Enqueue n packed steps (asynchronous; one graph replay per step).  A
+ * resident domain takes part in exactly its admitted number of steps. */
+int lbm_batch_step(lbm_batch *b, int n);
+
+/*
+ * Report domains whose admitted steps have all completed on the device
+ * since the last poll.  Non-blocking unless wait != 0 (then waits for all
+ * enqueued work).  done_slots receives up to max slot ids; *n_done their
+ * count.  A completed domain stays resident until lbm_batch_release.
+ */
+int lbm_batch_poll(lbm_batch *b, int wait, int *done_slots, int max, int *n_done);
+
+/* Release a completed slot: frees its budget, removes its tiles from the
+ * packed table, and returns the domain to stand-alone use (its status is
+ * LBM_ERR_UNSTABLE if any of its batched steps was unstable). */
+int lbm_batch_release(lbm_batch *b, int slot, lbm_domain **d);
+
+/* Number of resident slots, the step counter and the budget in use. */
+int lbm_batch_stats(const lbm_batch *b, int *resident, uint64_t *steps_enqueued, size_t *bytes_in_use);
+
+int lbm_batch_destroy(lbm_batch *b);
+
+/* -------------------------------------------------------------------- */
+/* Diagnostics                                                           */
+/* -------------------------------------------------------------------- */
+
+/* Host-only self checks of the index arithmetic and tile classification
+ * (no device call).  Returns LBM_OK or LBM_ERR_STATE with a message. */
+int lbm_selftest_host(void);
+
+/* Library version string. */
+const char *lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

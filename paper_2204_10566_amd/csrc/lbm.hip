@@ -1,0 +1,712 @@
+// lbm.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// A domain holds two population buffers (pull scheme: read one, write the
+// other, swap), the list of 64-cell tiles that contain updated cells, and
+// for tiles that touch a wall, inlet, box face or non-updated cell a 32-bit
+// link mask per cell.  Interior tiles (every cell updated, every link a
+// plain pull after periodic wrap) carry no mask and take the kernel's fast
+// path.  Steps are replayed from a captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lbm_device.hpp"
+#include "../../include/lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                            \
+    do {                                                                                                         \
+        hipError_t e_ = (expr);                                                                                  \
+        if (e_ != hipSuccess)                                                                                    \
+            return fail(LBM_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));                          \
+    } while (0)
+
+size_t storage_bytes(int st) { return st == LBM_FP32 ? 4 : 2; }
+
+FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f{};
+    uint32_t l = 0;
+    while ((1ull << l) < d)
+        ++l;
+    f.m = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 0 ? l - 1 : 0;
+    f.d = d;
+    return f;
+}
+
+bool updated(uint8_t fl) { return fl == LBM_FLUID || fl == LBM_OUTLET; }
+
+// Link classification of one cell (host copy of the boundary rules):
+// returns the wall mask (bit i: halfway bounce-back for population i,
+// kMaskInlet if any link comes from an inlet cell, kMaskSkip if the cell is
+// not updated) and the inlet mask.
+void classify_cell(const uint8_t *flags, int nx, int ny, int nz, unsigned per, uint64_t cell, uint32_t &wall,
+                   uint32_t &inl)
+{
+    wall = 0;
+    inl = 0;
+    const uint8_t self = flags[cell];
+    if (!updated(self)) {
+        wall = kMaskSkip;
+        return;
+    }
+    const int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((uint64_t)nx * ny));
+    for (int i = 0; i < Q; ++i) {
+        int sx = x - cx(i), sy = y - cy(i), sz = z - cz(i);
+        if (per & 1u)
+            sx = (sx + nx) % nx;
+        if (per & 2u)
+            sy = (sy + ny) % ny;
+        if (per & 4u)
+            sz = (sz + nz) % nz;
+        if (sx >= nx && !(per & 1u) && self == LBM_OUTLET)
+            sx = nx - 1;
+        if (sx < 0 || sx >= nx || sy < 0 || sy >= ny || sz < 0 || sz >= nz) {
+            wall |= 1u << i;
+            continue;
+        }
+        const uint8_t fs = flags[((uint64_t)sz * ny + sy) * nx + sx];
+        if (fs == LBM_SOLID) {
+            wall |= 1u << i;
+        } else if (fs == LBM_INLET) {
+            wall |= (1u << i) | kMaskInlet;
+            inl |= 1u << i;
+        }
+    }
+}
+
+struct Tiles {
+    std::vector<TileRec> recs;
+    std::vector<uint32_t> wall, inlet;
+    uint64_t n_updated = 0;
+};
+
+// Build the tile list in tile order.  Work is split over host threads by
+// contiguous tile ranges and concatenated in order.
+void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, Tiles &out)
+{
+    const uint64_t ncells = (uint64_t)nx * ny * nz;
+    const uint64_t ntiles = (ncells + 63) / 64;
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (ntiles < 4096)
+        nth = 1;
+    std::vector<Tiles> part(nth);
+    auto work = [&](unsigned p) {
+        const uint64_t t0 = ntiles * p / nth, t1 = ntiles * (p + 1) / nth;
+        Tiles &T = part[p];
+        uint32_t wl[64], il[64];
+        for (uint64_t t = t0; t < t1; ++t) {
+            bool any = false, plain = true;
+            for (int l = 0; l < 64; ++l) {
+                const uint64_t c = t * 64 + l;
+                if (c >= ncells) {
+                    wl[l] = kMaskSkip;
+                    il[l] = 0;
+                } else {
+                    classify_cell(flags, nx, ny, nz, per, c, wl[l], il[l]);
+                }
+                if (!(wl[l] & kMaskSkip)) {
+                    any = true;
+                    T.n_updated++;
+                }
+                if (wl[l])
+                    plain = false;
+            }
+            if (!any)
+                continue;
+            if (plain) {
+                T.recs.push_back({(uint32_t)t, -1});
+            } else {
+                T.recs.push_back({(uint32_t)t, (int32_t)(T.wall.size() / 64)});
+                T.wall.insert(T.wall.end(), wl, wl + 64);
+                T.inlet.insert(T.inlet.end(), il, il + 64);
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned p = 1; p < nth; ++p)
+        th.emplace_back(work, p);
+    work(0);
+    for (auto &t : th)
+        t.join();
+    for (unsigned p = 0; p < nth; ++p) {
+        const int32_t off = (int32_t)(out.wall.size() / 64);
+        for (TileRec r : part[p].recs) {
+            if (r.mask >= 0)
+                r.mask += off;
+            out.recs.push_back(r);
+        }
+        out.wall.insert(out.wall.end(), part[p].wall.begin(), part[p].wall.end());
+        out.inlet.insert(out.inlet.end(), part[p].inlet.begin(), part[p].inlet.end());
+        out.n_updated += part[p].n_updated;
+    }
+}
+
+constexpr int kGraphSteps = 16; // steps per captured graph (even: ends on the starting buffer)
+
+} // namespace
+
+struct lbm_domain {
+    int nx = 0, ny = 0, nz = 0, storage = 0;
+    unsigned periodic = 0;
+    uint64_t ncells = 0, P = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool own_buffers = true;
+    int device = 0;
+    char *buf[2] = {nullptr, nullptr};
+    int cur = 0; // buffer holding the current state
+    uint8_t *d_flags = nullptr;
+    TileRec *d_tiles = nullptr;
+    uint32_t *d_wall = nullptr, *d_inlet = nullptr;
+    float *d_uin = nullptr;
+    uint32_t *d_status = nullptr;
+    uint64_t ntiles = 0, nwall = 0, n_updated = 0;
+    double omega = 1.0, omega_b = 1.0, omega_h = 1.0;
+    bool unstable = false;
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    bool graph_dirty = true;
+    std::vector<TileRec> h_tiles; // host copy of the tile list (batch tables are built from it)
+    lbm_batch *batch = nullptr;    // resident in this batch
+    uint64_t device_bytes = 0;
+};
+
+namespace {
+
+KDomain kdomain(const lbm_domain *d)
+{
+    KDomain k{};
+    k.buf[0] = d->buf[0];
+    k.buf[1] = d->buf[1];
+    k.wall = d->d_wall;
+    k.inlet = d->d_inlet;
+    k.uin = d->d_uin;
+    k.status = d->d_status;
+    k.P = (uint32_t)d->P;
+    k.pbytes = (uint32_t)(d->P * storage_bytes(d->storage));
+    k.nx = d->nx;
+    k.ny = d->ny;
+    k.nz = d->nz;
+    k.ncells = (uint32_t)d->ncells;
+    k.dnx = make_fastdiv(d->nx);
+    k.dny = make_fastdiv(d->ny);
+    k.periodic = d->periodic;
+    k.omega = (float)d->omega;
+    k.omega_b = (float)d->omega_b;
+    k.omega_h = (float)d->omega_h;
+    return k;
+}
+
+uint32_t grid8(uint64_t blocks) { return (uint32_t)((blocks + 7) / 8 * 8); }
+
+template <int ST, bool H>
+hipError_t launch_step_t(const lbm_domain *d, uint32_t src)
+{
+    const KDomain k = kdomain(d);
+    const uint32_t blocks = grid8((d->ntiles + 3) / 4);
+    hipLaunchKernelGGL((k_stream_collide<ST, H>), dim3(blocks), dim3(256), 0, d->stream, k, d->d_tiles,
+                       (uint32_t)d->ntiles, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const lbm_domain *d, uint32_t src)
+{
+    if (d->ntiles == 0)
+        return hipSuccess;
+    const bool h1 = d->omega_h == 1.0;
+    switch (d->storage) {
+    case LBM_FP32:
+        return h1 ? launch_step_t<ST_FP32, true>(d, src) : launch_step_t<ST_FP32, false>(d, src);
+    case LBM_FP16S:
+        return h1 ? launch_step_t<ST_FP16S, true>(d, src) : launch_step_t<ST_FP16S, false>(d, src);
+    default:
+        return h1 ? launch_step_t<ST_BF16S, true>(d, src) : launch_step_t<ST_BF16S, false>(d, src);
+    }
+}
+
+template <typename F> void dispatch_storage(int st, F &&f)
+{
+    if (st == LBM_FP32)
+        f(std::integral_constant<int, ST_FP32>{});
+    else if (st == LBM_FP16S)
+        f(std::integral_constant<int, ST_FP16S>{});
+    else
+        f(std::integral_constant<int, ST_BF16S>{});
+}
+
+int sync_status(lbm_domain *d)
+{
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    uint32_t st = 0;
+    HIP_TRY(hipMemcpy(&st, d->d_status, sizeof st, hipMemcpyDeviceToHost));
+    if (st)
+        d->unstable = true;
+    return LBM_OK;
+}
+
+int check_domain(const lbm_domain *d)
+{
+    if (!d)
+        return fail(LBM_ERR_ARG, "null domain");
+    return LBM_OK;
+}
+
+void release_graph(lbm_domain *d)
+{
+    if (d->graph)
+        (void)hipGraphExecDestroy(d->graph);
+    if (d->graph_def)
+        (void)hipGraphDestroy(d->graph_def);
+    d->graph = nullptr;
+    d->graph_def = nullptr;
+    d->graph_dirty = true;
+}
+
+void free_domain(lbm_domain *d)
+{
+    release_graph(d);
+    if (d->own_buffers) {
+        (void)hipFree(d->buf[0]);
+        (void)hipFree(d->buf[1]);
+    }
+    (void)hipFree(d->d_flags);
+    (void)hipFree(d->d_tiles);
+    (void)hipFree(d->d_wall);
+    (void)hipFree(d->d_inlet);
+    (void)hipFree(d->d_uin);
+    (void)hipFree(d->d_status);
+    if (d->own_stream && d->stream)
+        (void)hipStreamDestroy(d->stream);
+    delete d;
+}
+
+int init_eq(lbm_domain *d, const float *rho_dev, const float *u_dev)
+{
+    const KDomain k = kdomain(d);
+    const uint32_t blocks = (uint32_t)((d->P + 255) / 256);
+    dispatch_storage(d->storage, [&](auto st) {
+        hipLaunchKernelGGL((k_init_eq<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, d->d_flags,
+                           rho_dev, u_dev, (uint32_t)d->cur);
+    });
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemsetAsync(d->d_status, 0, sizeof(uint32_t), d->stream));
+    d->unstable = false;
+    return LBM_OK;
+}
+
+int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage, void *hip_stream, void *fa,
+           void *fb, lbm_domain **out)
+{
+    if (!out)
+        return fail(LBM_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (!flags)
+        return fail(LBM_ERR_ARG, "flags is null");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 65535 || ny > 65535 || nz > 65535)
+        return fail(LBM_ERR_ARG, "bad grid %d x %d x %d", nx, ny, nz);
+    if (storage < LBM_FP32 || storage > LBM_BF16S)
+        return fail(LBM_ERR_ARG, "bad storage %d", storage);
+    if (periodic > 7u)
+        return fail(LBM_ERR_ARG, "bad periodic mask %u", periodic);
+    const uint64_t ncells = (uint64_t)nx * ny * nz;
+    const uint64_t P = (ncells + 63) / 64 * 64;
+    const uint64_t bufbytes = (uint64_t)Q * P * storage_bytes(storage);
+    if (bufbytes >= (1ull << 32))
+        return fail(LBM_ERR_ARG, "domain of %llu cells needs %llu bytes per buffer; the limit is 4 GiB",
+                    (unsigned long long)ncells, (unsigned long long)bufbytes);
+    for (uint64_t c = 0; c < ncells; ++c) {
+        const uint8_t f = flags[c];
+        if (f > LBM_OUTLET)
+            return fail(LBM_ERR_ARG, "bad flag %u at cell %llu", f, (unsigned long long)c);
+        if (f == LBM_OUTLET && ((c % nx) != (uint64_t)nx - 1 || (periodic & 1u)))
+            return fail(LBM_ERR_ARG, "outlet cell %llu not on the last x plane of a non-periodic x axis",
+                        (unsigned long long)c);
+    }
+    Tiles T;
+    build_tiles(flags, nx, ny, nz, periodic, T);
+
+    lbm_domain *d = new lbm_domain();
+    d->nx = nx;
+    d->ny = ny;
+    d->nz = nz;
+    d->storage = storage;
+    d->periodic = periodic;
+    d->ncells = ncells;
+    d->P = P;
+    d->ntiles = T.recs.size();
+    d->nwall = T.wall.size() / 64;
+    d->n_updated = T.n_updated;
+    d->h_tiles = T.recs;
+    auto bail = [&](int code) {
+        free_domain(d);
+        return code;
+    };
+    if (hipGetDevice(&d->device) != hipSuccess)
+        return bail(fail(LBM_ERR_DEVICE, "no HIP device"));
+    if (hip_stream) {
+        d->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(LBM_ERR_DEVICE, "hipStreamCreate failed"));
+        d->own_stream = true;
+    }
+    auto dmalloc = [&](void **p, size_t n) -> bool {
+        if (n == 0) {
+            *p = nullptr;
+            return true;
+        }
+        if (hipMalloc(p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        d->device_bytes += n;
+        return true;
+    };
+    if (fa && fb) {
+        d->own_buffers = false;
+        d->buf[0] = (char *)fa;
+        d->buf[1] = (char *)fb;
+        if (((uintptr_t)fa | (uintptr_t)fb) & 255u)
+            return bail(fail(LBM_ERR_ARG, "adopted buffers must be 256-byte aligned"));
+        d->device_bytes += 2 * bufbytes;
+    } else if (!dmalloc((void **)&d->buf[0], bufbytes) || !dmalloc((void **)&d->buf[1], bufbytes)) {
+        return bail(fail(LBM_ERR_OOM, "population buffers (2 x %llu bytes)", (unsigned long long)bufbytes));
+    }
+    if (!dmalloc((void **)&d->d_flags, ncells) || !dmalloc((void **)&d->d_tiles, T.recs.size() * sizeof(TileRec)) ||
+        !dmalloc((void **)&d->d_wall, T.wall.size() * 4) || !dmalloc((void **)&d->d_inlet, T.inlet.size() * 4) ||
+        !dmalloc((void **)&d->d_status, sizeof(uint32_t)))
+        return bail(fail(LBM_ERR_OOM, "domain tables"));
+    if (hipMemcpy(d->d_flags, flags, ncells, hipMemcpyHostToDevice) != hipSuccess ||
+        (d->ntiles && hipMemcpy(d->d_tiles, T.recs.data(), T.recs.size() * sizeof(TileRec),
+                                hipMemcpyHostToDevice) != hipSuccess) ||
+        (d->nwall && (hipMemcpy(d->d_wall, T.wall.data(), T.wall.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                      hipMemcpy(d->d_inlet, T.inlet.data(), T.inlet.size() * 4, hipMemcpyHostToDevice) !=
+                          hipSuccess)))
+        return bail(fail(LBM_ERR_DEVICE, "upload of domain tables failed"));
+    d->omega = d->omega_b = 1.0 / 0.6;
+    d->omega_h = 1.0;
+    d->cur = 0;
+    int rc = init_eq(d, nullptr, nullptr);
+    if (rc == LBM_OK && hipStreamSynchronize(d->stream) != hipSuccess)
+        rc = fail(LBM_ERR_DEVICE, "initialisation failed");
+    if (rc != LBM_OK)
+        return bail(rc);
+    *out = d;
+    return LBM_OK;
+}
+
+int capture_graph(lbm_domain *d)
+{
+    release_graph(d);
+    hipStream_t s = d->stream;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
+        e = launch_step(d, (uint32_t)(k & 1));
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return fail(LBM_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    d->graph_def = g;
+    HIP_TRY(hipGraphInstantiate(&d->graph, g, nullptr, nullptr, 0));
+    d->graph_dirty = false;
+    return LBM_OK;
+}
+
+} // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+const char *lbm_version(void) { return "lbm-d3q27-chm gfx950 0.1"; }
+
+int lbm_create_domain(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
+                      void *hip_stream, lbm_domain **out)
+{
+    return create(flags, nx, ny, nz, periodic, storage, hip_stream, nullptr, nullptr, out);
+}
+
+int lbm_create_domain_ext(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
+                          void *hip_stream, void *f_a, void *f_b, lbm_domain **out)
+{
+    if (!f_a || !f_b)
+        return fail(LBM_ERR_ARG, "adopted buffers are null");
+    return create(flags, nx, ny, nz, periodic, storage, hip_stream, f_a, f_b, out);
+}
+
+int lbm_set_rates(lbm_domain *d, double omega, double omega_bulk, double omega_high)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!(omega >= 0 && omega <= 2) || !(omega_bulk >= 0 && omega_bulk <= 2) ||
+        !(omega_high >= 0 && omega_high <= 2))
+        return fail(LBM_ERR_ARG, "rates must lie in [0, 2]");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    d->omega = omega;
+    d->omega_b = omega_bulk;
+    d->omega_h = omega_high;
+    d->graph_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_set_params(lbm_domain *d, double tau, double omega_bulk, double omega_high)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!(tau > 0.5) || !std::isfinite(tau))
+        return fail(LBM_ERR_ARG, "tau must be > 0.5");
+    if (!(omega_bulk > 0 && omega_bulk < 2))
+        return fail(LBM_ERR_ARG, "omega_bulk must lie in (0, 2)");
+    if (!(omega_high > 0 && omega_high <= 2))
+        return fail(LBM_ERR_ARG, "omega_high must lie in (0, 2]");
+    return lbm_set_rates(d, 1.0 / tau, omega_bulk, omega_high);
+}
+
+int lbm_set_inlet(lbm_domain *d, const float *u_in)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!u_in)
+        return fail(LBM_ERR_ARG, "u_in is null");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    if (!d->d_uin) {
+        if (hipMalloc((void **)&d->d_uin, 3 * d->P * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            d->d_uin = nullptr;
+            return fail(LBM_ERR_OOM, "inlet velocity buffer");
+        }
+        d->device_bytes += 3 * d->P * sizeof(float);
+        d->graph_dirty = true;
+    }
+    for (int a = 0; a < 3; ++a)
+        HIP_TRY(hipMemcpy(d->d_uin + a * d->P, u_in + a * d->ncells, d->ncells * sizeof(float),
+                          hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
+int lbm_init_fields(lbm_domain *d, const float *rho, const float *u)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    float *dr = nullptr, *du = nullptr;
+    int rc = LBM_OK;
+    if (rho && hipMalloc((void **)&dr, d->ncells * sizeof(float)) != hipSuccess)
+        rc = fail(LBM_ERR_OOM, "staging buffer");
+    if (rc == LBM_OK && u && hipMalloc((void **)&du, 3 * d->ncells * sizeof(float)) != hipSuccess)
+        rc = fail(LBM_ERR_OOM, "staging buffer");
+    if (rc == LBM_OK && rho && hipMemcpy(dr, rho, d->ncells * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(LBM_ERR_DEVICE, "upload of rho failed");
+    if (rc == LBM_OK && u && hipMemcpy(du, u, 3 * d->ncells * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(LBM_ERR_DEVICE, "upload of u failed");
+    if (rc == LBM_OK)
+        rc = init_eq(d, dr, du);
+    if (rc == LBM_OK && hipStreamSynchronize(d->stream) != hipSuccess)
+        rc = fail(LBM_ERR_DEVICE, "initialisation failed");
+    (void)hipFree(dr);
+    (void)hipFree(du);
+    return rc;
+}
+
+int lbm_step(lbm_domain *d, int n)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (n < 0)
+        return fail(LBM_ERR_ARG, "negative step count");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    if (d->unstable)
+        return fail(LBM_ERR_UNSTABLE, "domain went unstable earlier; re-initialise it");
+    if (d->ntiles == 0) // nothing is updated, the state stays as it is
+        return LBM_OK;
+    int left = n;
+    if (left > 0 && d->cur == 1) {
+        HIP_TRY(launch_step(d, 1));
+        d->cur = 0;
+        --left;
+    }
+    if (left >= kGraphSteps) {
+        if (d->graph_dirty)
+            if (int rc = capture_graph(d))
+                return rc;
+        while (left >= kGraphSteps) {
+            HIP_TRY(hipGraphLaunch(d->graph, d->stream));
+            left -= kGraphSteps;
+        }
+    }
+    while (left > 0) {
+        HIP_TRY(launch_step(d, (uint32_t)d->cur));
+        d->cur ^= 1;
+        --left;
+    }
+    if (int rc = sync_status(d))
+        return rc;
+    if (d->unstable)
+        return fail(LBM_ERR_UNSTABLE, "a step produced rho <= 0 or a non-finite value");
+    return LBM_OK;
+}
+
+int lbm_get_moments_device(lbm_domain *d, float *rho_dev, float *u_dev)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!rho_dev || !u_dev)
+        return fail(LBM_ERR_ARG, "null output");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    const KDomain k = kdomain(d);
+    const uint32_t blocks = (uint32_t)((d->ncells + 255) / 256);
+    dispatch_storage(d->storage, [&](auto st) {
+        hipLaunchKernelGGL((k_moments<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, d->d_flags,
+                           (uint32_t)d->cur, rho_dev, u_dev);
+    });
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    return LBM_OK;
+}
+
+int lbm_get_moments(lbm_domain *d, float *rho, float *u)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!rho || !u)
+        return fail(LBM_ERR_ARG, "null output");
+    float *dr = nullptr;
+    if (hipMalloc((void **)&dr, 4 * d->ncells * sizeof(float)) != hipSuccess)
+        return fail(LBM_ERR_OOM, "staging buffer");
+    int rc = lbm_get_moments_device(d, dr, dr + d->ncells);
+    if (rc == LBM_OK && (hipMemcpy(rho, dr, d->ncells * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+                         hipMemcpy(u, dr + d->ncells, 3 * d->ncells * sizeof(float), hipMemcpyDeviceToHost) !=
+                             hipSuccess))
+        rc = fail(LBM_ERR_DEVICE, "download failed");
+    (void)hipFree(dr);
+    return rc;
+}
+
+int lbm_get_populations(lbm_domain *d, float *f)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!f)
+        return fail(LBM_ERR_ARG, "null output");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    float *df = nullptr;
+    if (hipMalloc((void **)&df, (size_t)Q * d->ncells * sizeof(float)) != hipSuccess)
+        return fail(LBM_ERR_OOM, "staging buffer");
+    const KDomain k = kdomain(d);
+    const uint32_t blocks = (uint32_t)((d->ncells + 255) / 256);
+    dispatch_storage(d->storage, [&](auto st) {
+        hipLaunchKernelGGL((k_export<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k,
+                           (uint32_t)d->cur, df);
+    });
+    int rc = LBM_OK;
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(d->stream) != hipSuccess ||
+        hipMemcpy(f, df, (size_t)Q * d->ncells * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(LBM_ERR_DEVICE, "population export failed");
+    (void)hipFree(df);
+    return rc;
+}
+
+int lbm_set_populations(lbm_domain *d, const float *f)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!f)
+        return fail(LBM_ERR_ARG, "null input");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    float *df = nullptr;
+    if (hipMalloc((void **)&df, (size_t)Q * d->ncells * sizeof(float)) != hipSuccess)
+        return fail(LBM_ERR_OOM, "staging buffer");
+    int rc = LBM_OK;
+    if (hipMemcpy(df, f, (size_t)Q * d->ncells * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(LBM_ERR_DEVICE, "upload failed");
+    if (rc == LBM_OK) {
+        const KDomain k = kdomain(d);
+        const uint32_t blocks = (uint32_t)((d->ncells + 255) / 256);
+        dispatch_storage(d->storage, [&](auto st) {
+            hipLaunchKernelGGL((k_import<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k,
+                               (uint32_t)d->cur, df);
+        });
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(d->stream) != hipSuccess)
+            rc = fail(LBM_ERR_DEVICE, "population import failed");
+    }
+    (void)hipFree(df);
+    return rc;
+}
+
+int lbm_domain_get_info(const lbm_domain *d, lbm_domain_info *info)
+{
+    if (!d || !info)
+        return fail(LBM_ERR_ARG, "null argument");
+    info->nx = d->nx;
+    info->ny = d->ny;
+    info->nz = d->nz;
+    info->storage = d->storage;
+    info->periodic = d->periodic;
+    info->ncells = d->ncells;
+    info->plane_stride = d->P;
+    info->n_updated = d->n_updated;
+    info->n_tiles = d->ntiles;
+    info->n_wall_tiles = d->nwall;
+    info->device_bytes = d->device_bytes;
+    info->bytes_per_cell_update = 2ull * Q * storage_bytes(d->storage);
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_domain *d)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch; release it first");
+    (void)hipStreamSynchronize(d->stream);
+    free_domain(d);
+    return LBM_OK;
+}
+
+} // extern "C"
+
+#include "lbm_batch.inc"
+#include "lbm_selftest.inc"

@@ -65,6 +65,22 @@ def taylor_green_2d_velocity(nx: int, ny: int, u0: float) -> np.ndarray:
     return u
 
 
+def random_populations(shape, seed: int, drift: float = 0.05, noise: float = 0.02) -> np.ndarray:
+    """A positive random population field [27, nz, ny, nx]: the lattice
+    weights w_i times (1 + 3 c_i . v) for a random drift v per cell, times
+    (1 + noise U(-1, 1)) per population.  An arbitrary test state, not an
+    equilibrium."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = np.array([(i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1) for i in range(27)], dtype=np.float64)
+    w1 = {-1: 1.0 / 6.0, 0: 2.0 / 3.0, 1: 1.0 / 6.0}
+    w = np.array([w1[a] * w1[b] * w1[g] for a, b, g in c.astype(int)])
+    v = drift * rng.uniform(-1.0, 1.0, (3,) + tuple(shape))
+    cv = np.tensordot(c, v, axes=(1, 0))
+    f = w.reshape((27,) + (1,) * len(shape)) * (1.0 + 3.0 * cv)
+    f *= 1.0 + noise * rng.uniform(-1.0, 1.0, f.shape)
+    return f
+
+
 # ---------------------------------------------------------------------------
 # Channel between two walls normal to y (periodic in x and z)
 # ---------------------------------------------------------------------------

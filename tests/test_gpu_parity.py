@@ -1,0 +1,262 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances (FP32 storage and arithmetic against FP64):
+  - Taylor-Green 32^3, u0 = 0.05, tau = 0.6, 100 steps: velocity relative L2
+    <= 1e-5 (the stated target);
+  - one step from random populations: max |f_gpu - f_oracle| <= 4e-7, about
+    ten FP32 ulps of the largest population (8/27), which bounds the rounding
+    of the ~600 FP32 operations of one update;
+  - nozzle geometries: velocity error relative to the peak velocity;
+  - FP16 shifted storage: velocity relative L2 <= 1e-3.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2204_10566_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2204_10566_amd import capi
+
+    return capi
+
+
+def rel_l2(a, b, mask=None):
+    if mask is not None:
+        a = a[..., mask]
+        b = b[..., mask]
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def updated(fl):
+    return (fl == I.FLUID) | (fl == I.OUTLET)
+
+
+def run_gpu(capi, fl, periodic, steps, tau=None, rates=None, u0=None, rho0=None, uin=None, storage="fp32",
+            pops=None):
+    d = capi.Domain(fl, periodic=periodic, storage=storage)
+    if rates is not None:
+        d.set_rates(*rates)
+    else:
+        d.set_params(tau, 1.0 / tau, 1.0)
+    if uin is not None:
+        d.set_inlet(uin)
+    d.init_fields(rho0, u0)
+    if pops is not None:
+        d.set_populations(pops)
+    if steps:
+        d.step(steps)
+    return d
+
+
+def test_init_equilibrium_matches_oracle(capi, orc):
+    """GPU product-form equilibrium == oracle Hermite-sum equilibrium."""
+    say("init equilibrium 12x10x8")
+    fl = np.zeros((8, 10, 12), np.uint8)
+    rng = np.random.default_rng(11)
+    rho = 1 + 0.05 * rng.uniform(-1, 1, fl.shape)
+    u = 0.15 * rng.uniform(-1, 1, (3,) + fl.shape)
+    d = run_gpu(capi, fl, 7, 0, tau=0.6, u0=u, rho0=rho)
+    fg = d.populations()
+    fo = orc.init_fields(fl, rho.astype(np.float32), u.astype(np.float32))
+    assert np.abs(fg - fo).max() < 1e-7
+
+
+@pytest.mark.parametrize("storage", ["fp32"])
+def test_tgv32_100_steps(capi, orc, storage):
+    """32^3 periodic Taylor-Green vortex, u0 = 0.05, rho = 1, tau = 0.6,
+    paper's rates (omega_bulk = 1/tau, omega_high = 1), 100 steps."""
+    n, tau = 32, 0.6
+    fl = I.periodic_box(n)
+    u0 = I.taylor_green_velocity(n, n, n, 0.05)
+    say(f"tgv32 {storage} 100 steps")
+    d = run_gpu(capi, fl, 7, 100, tau=tau, u0=u0, storage=storage)
+    rg, ug = d.moments()
+    f = orc.init_fields(fl, None, u0.astype(np.float32))
+    st, f = orc.step(fl, f, orc.rates_vector(1 / tau), 100, periodic=7)
+    assert st == 0
+    ro, uo = orc.moments(fl, f)
+    e_u = rel_l2(ug, uo)
+    e_p = float(np.linalg.norm(rg - ro) / np.linalg.norm(ro - ro.mean()))
+    say(f"tgv32 {storage}: e_u={e_u:.3e} e_p={e_p:.3e}")
+    assert e_u <= 1e-5
+    # global mass and momentum drift of the FP32 state
+    assert abs(rg.sum() / ro.sum() - 1) < 1e-6
+    assert np.abs((rg * ug).sum(axis=(1, 2, 3))).max() < 1e-3 * 1e-3 * rg.size
+
+
+def random_pops(orc, fl, seed):
+    # FP32-representable, so both sides start from identical values
+    return I.random_populations(fl.shape, seed).astype(np.float32).astype(np.float64)
+
+
+def mixed_geometry():
+    """x: inlet plane, fluid, outlet plane; y: walls; z periodic; a solid
+    obstacle and a ragged cell count (not a multiple of 64)."""
+    nz, ny, nx = 5, 9, 23
+    fl = np.zeros((nz, ny, nx), np.uint8)
+    fl[:, 0, :] = I.SOLID
+    fl[:, -1, :] = I.SOLID
+    fl[:, 1:-1, 0] = I.INLET
+    fl[:, 1:-1, -1] = I.OUTLET
+    fl[2, 3:5, 8:11] = I.SOLID
+    return fl
+
+
+@pytest.mark.parametrize("rates", [(1 / 0.6, 1 / 0.6, 1.0), (1 / 0.51, 0.7, 1.3), (1.9, 1.2, 0.4)])
+def test_one_step_random_populations(capi, orc, rates):
+    """Populations after one and after five steps from random states on a
+    geometry with every boundary kind, with general rates."""
+    fl = mixed_geometry()
+    rng = np.random.default_rng(3)
+    uin = np.zeros((3,) + fl.shape)
+    uin[:, fl == I.INLET] = 0.02 * rng.uniform(-1, 1, (3, int((fl == I.INLET).sum())))
+    uin = uin.astype(np.float32)
+    f0 = random_pops(orc, fl, 5)
+    upd = updated(fl)
+    for steps in (1, 5):
+        say(f"random pops rates={rates} steps={steps}")
+        d = run_gpu(capi, fl, 4, steps, rates=rates, uin=uin, pops=f0)
+        fg = d.populations()
+        st, fo = orc.step(fl, f0, orc.rates_vector(rates[0], rates[1], rates[2]), steps, periodic=4, uin=uin)
+        assert st == 0
+        err = np.abs(fg[:, upd] - fo[:, upd]).max()
+        say(f"  max abs err {err:.3e}")
+        assert err <= 4e-7 * steps
+
+
+def test_small_nozzle_run(capi, orc):
+    """A scaled-down nozzle (inlet, cone, throat, sudden expansion, outlet)
+    run 200 steps from the plug-flow start; velocity error relative to the
+    peak velocity."""
+    cfg = I.small_nozzle(n=24, length=160, R=8.0, r_throat=3.0, Re=100.0)
+    fl, tau = cfg["flags"], cfg["tau"]
+    say(f"small nozzle 24x24x160 tau={tau:.5f} 200 steps")
+    d = run_gpu(capi, fl, 0, 200, tau=tau, u0=cfg["u0"].astype(np.float32), uin=cfg["uin"].astype(np.float32))
+    rg, ug = d.moments()
+    f = orc.init_fields(fl, None, cfg["u0"].astype(np.float32))
+    st, f = orc.step(fl, f, orc.rates_vector(1 / tau), 200, periodic=0, uin=cfg["uin"].astype(np.float32))
+    assert st == 0
+    ro, uo = orc.moments(fl, f)
+    upd = updated(fl)
+    e_u = rel_l2(ug, uo, upd)
+    e_max = float(np.abs(ug - uo)[:, upd].max() / np.abs(uo[:, upd]).max())
+    say(f"small nozzle: e_u={e_u:.3e} max/peak={e_max:.3e}")
+    assert e_u <= 1e-4 and e_max <= 1e-4
+
+
+@pytest.mark.parametrize("which", ["re500"])
+def test_full_size_nozzle_sampled(capi, orc, which):
+    """Full-size nozzle (96x96x768), 3 steps in the benchmark's launch
+    configuration; populations compared at sampled cells (inlet-adjacent,
+    outlet, wall-adjacent, throat, random) against the oracle's
+    dependency-cone run from the same initial fields."""
+    cfg = I.nozzle_config(which)
+    fl, tau = cfg["flags"], cfg["tau"]
+    u0 = cfg["u0"].astype(np.float32)
+    uin = cfg["uin"].astype(np.float32)
+    say(f"nozzle {which} {fl.shape} 3 steps")
+    d = run_gpu(capi, fl, 0, 3, tau=tau, u0=u0, uin=uin)
+    fg = d.populations().reshape(27, -1)
+    upd = np.flatnonzero(updated(fl).ravel())
+    nz_, ny_, nx_ = fl.shape
+    xs = upd % nx_
+    rng = np.random.default_rng(0)
+    picks = [upd[xs == 1][:40], upd[xs == nx_ - 1][:40], rng.choice(upd, 120, replace=False)]
+    # cells next to a wall
+    solid = fl.ravel() == I.SOLID
+    near = upd[solid[np.clip(upd + nx_, 0, fl.size - 1)] | solid[np.clip(upd - nx_, 0, fl.size - 1)]]
+    picks.append(rng.choice(near, 60, replace=False))
+    cells = np.unique(np.concatenate(picks))
+    st, fo = orc.run_cells(fl, cells, orc.rates_vector(1 / tau), 3, periodic=0, uin=uin, u0=u0)
+    assert st == 0
+    err = np.abs(fg[:, cells] - fo).max()
+    say(f"nozzle {which}: {cells.size} cells, max abs err {err:.3e}")
+    assert err <= 1e-6
+
+
+def test_fp16_shifted_tgv32(capi, orc):
+    n, tau = 32, 0.6
+    fl = I.periodic_box(n)
+    u0 = I.taylor_green_velocity(n, n, n, 0.05)
+    say("tgv32 fp16s / bf16s 100 steps")
+    f = orc.init_fields(fl, None, u0.astype(np.float32))
+    st, f = orc.step(fl, f, orc.rates_vector(1 / tau), 100, periodic=7)
+    ro, uo = orc.moments(fl, f)
+    res = {}
+    for storage in ("fp16s", "bf16s"):
+        d = run_gpu(capi, fl, 7, 100, tau=tau, u0=u0, storage=storage)
+        rg, ug = d.moments()
+        res[storage] = (rel_l2(ug, uo), float(np.linalg.norm(rg - ro) / np.linalg.norm(ro - ro.mean())))
+        say(f"tgv32 {storage}: e_u={res[storage][0]:.3e} e_p={res[storage][1]:.3e}")
+    assert res["fp16s"][0] <= 1e-3
+    assert res["bf16s"][0] <= 2e-2
+
+
+def test_empty_and_degenerate_domains(capi, orc):
+    """All-solid domain (no tiles), one-cell-thick periodic slab, a 1x1x1
+    periodic cell, and a ragged 7x5x3 box."""
+    say("degenerate domains")
+    d = capi.Domain(np.ones((3, 4, 5), np.uint8), periodic=0)
+    d.set_params(0.7)
+    d.step(10)
+    assert d.info().n_tiles == 0
+    for shape in [(1, 6, 10), (1, 1, 1), (3, 5, 7)]:
+        fl = np.zeros(shape, np.uint8)
+        f0 = random_pops(orc, fl, 9)
+        dd = run_gpu(capi, fl, 7, 4, rates=(1 / 0.55, 1.1, 1.0), pops=f0)
+        st, fo = orc.step(fl, f0, orc.rates_vector(1 / 0.55, 1.1, 1.0), 4, periodic=7)
+        assert np.abs(dd.populations() - fo).max() <= 2e-6
+
+
+def test_unstable_run_reports_error(capi):
+    """A state with negative density is reported as LBM_ERR_UNSTABLE and the
+    error stays until the fields are re-initialised."""
+    say("unstable detection")
+    fl = np.zeros((4, 4, 4), np.uint8)
+    d = capi.Domain(fl, periodic=7)
+    d.set_params(0.6)
+    f = -np.ones((27,) + fl.shape, np.float32) * 0.01
+    d.set_populations(f)
+    assert d.step_status(1) == capi.ERR_UNSTABLE
+    assert d.step_status(1) == capi.ERR_UNSTABLE
+    d.init_fields()
+    assert d.step_status(3) == capi.OK
+
+
+def test_adopted_torch_buffers_and_stream(capi, orc):
+    """Population buffers and the stream come from torch."""
+    import torch
+
+    n = 16
+    fl = I.periodic_box(n)
+    u0 = I.taylor_green_velocity(n, n, n, 0.03).astype(np.float32)
+    P = (fl.size + 63) // 64 * 64
+    a = torch.empty(27 * P, dtype=torch.float32, device="cuda")
+    b = torch.empty(27 * P, dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    say("torch-adopted buffers 16^3")
+    d = capi.Domain(fl, periodic=7, storage="fp32", stream=s.cuda_stream, buffers=(a.data_ptr(), b.data_ptr()))
+    d.set_params(0.7)
+    d.init_fields(None, u0)
+    d.step(20)
+    rho = torch.empty(fl.size, dtype=torch.float32, device="cuda")
+    u = torch.empty(3 * fl.size, dtype=torch.float32, device="cuda")
+    d.moments_device(rho.data_ptr(), u.data_ptr())
+    ug = u.cpu().numpy().reshape((3,) + fl.shape)
+    f = orc.init_fields(fl, None, u0)
+    st, f = orc.step(fl, f, orc.rates_vector(1 / 0.7), 20, periodic=7)
+    _, uo = orc.moments(fl, f)
+    assert rel_l2(ug, uo) <= 1e-5
+    d.destroy()
