@@ -67,6 +67,28 @@ def time_steps(capi, torch, cfg, storage, steps, warmup, stream):
     return info, ms, rc, rho, u
 
 
+def copy_ceiling(torch, stream, nbytes, reps=20):
+    """A plain device-to-device copy moving the same number of bytes as one
+    step (half read, half written): the practical HBM ceiling on this machine,
+    and the reference kernel for scaling the rocprofv3 byte counters."""
+    n = int(nbytes // 2 // 4)
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            dst.copy_(src)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1), "bytes_per_copy": 2 * n * 4, "us_per_copy": round(ms * 1e3, 2)}
+
+
 def cpu_baseline(cfg, nsteps=3):
     import numpy as np
 
@@ -130,6 +152,8 @@ def main():
     log(f"{args.storage}: {ms_step * 1e3:.2f} us/step, {mlups:.0f} fluid MLUPS, {achieved:.0f} GB/s algorithmic, "
         f"status {rc}")
     traffic = read_traffic("stream_collide", args.storage)
+    copy = copy_ceiling(torch, stream, n_upd * bpc)
+    log(f"plain copy of {copy['bytes_per_copy'] / 1e6:.0f} MB: {copy['gbs']:.0f} GB/s")
 
     out = {
         "metric": METRIC,
@@ -165,6 +189,8 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
             "bytes_per_fluid_cell": bpc,
+            "copy_ceiling_gbs": copy["gbs"],
+            "frac_of_copy": round(achieved / copy["gbs"], 4),
         },
     }
     if not args.no_variants and args.storage == "fp32":

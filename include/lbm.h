@@ -24,8 +24,12 @@
  *     the axial (inlet-to-outlet) direction.
  *   - Population order: i = (cx+1) + 3(cy+1) + 9(cz+1) for the velocity
  *     c_i = (cx, cy, cz) in {-1,0,1}^3; the opposite of i is 26 - i.
- *   - Populations are stored structure-of-arrays, f[i*P + cell], with a
- *     plane stride P = ncells rounded up to a multiple of 64.
+ *   - Populations are stored tile-major: cells are grouped into 64-cell
+ *     tiles of the linear index, and the 27 populations of a tile form one
+ *     block (population i of the tile's cell l at element 64*i + l of the
+ *     block).  P = lbm_plane_stride(...) is ncells rounded up to whole
+ *     tiles; a buffer holds 27*P elements.  lbm_get_populations and
+ *     lbm_set_populations convert to and from a plain [i][cell] layout.
  *   - The stored state is the post-collision population of the last step.
  *   - Calls on one domain are not thread-safe; different domains may be
  *     used from different threads.  All work is issued on the domain's
@@ -107,11 +111,16 @@ typedef struct lbm_domain_info {
 int lbm_create_domain(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
                       void *hip_stream, lbm_domain **out);
 
+/* P (in cells) of a domain of nx*ny*nz cells: ncells rounded up to a
+ * multiple of 64.  A population buffer holds 27*P elements.  0 for invalid
+ * sizes. */
+uint64_t lbm_plane_stride(int nx, int ny, int nz);
+
 /*
  * As lbm_create_domain, but adopts two caller-allocated device buffers of
- * 27*P elements each (sizeof(storage) bytes per element, 256-byte aligned),
- * e.g. from torch.  The caller keeps ownership; the buffers must outlive
- * the domain.  P is ncells rounded up to a multiple of 64.
+ * 27*P elements each (P = lbm_plane_stride(nx, ny, nz); sizeof(storage)
+ * bytes per element, 256-byte aligned), e.g. from torch.  The caller keeps
+ * ownership; the buffers must outlive the domain.
  */
 int lbm_create_domain_ext(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
                           void *hip_stream, void *f_a, void *f_b, lbm_domain **out);

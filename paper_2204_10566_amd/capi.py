@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm.so")
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 
 FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
 FP32, FP16S, BF16S = 0, 1, 2
@@ -69,6 +69,7 @@ SIGNATURES = {
     "lbm_batch_release": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
     "lbm_batch_stats": (ctypes.c_int, [_vp, _ip, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_size_t)]),
     "lbm_batch_destroy": (ctypes.c_int, [_vp]),
+    "lbm_plane_stride": (ctypes.c_uint64, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbm_selftest_host": (ctypes.c_int, []),
     "lbm_version": (ctypes.c_char_p, []),
 }

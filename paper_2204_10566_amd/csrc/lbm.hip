@@ -212,7 +212,8 @@ KDomain kdomain(const lbm_domain *d)
     k.uin = d->d_uin;
     k.status = d->d_status;
     k.P = (uint32_t)d->P;
-    k.pbytes = (uint32_t)(d->P * storage_bytes(d->storage));
+    k.tbytes = (uint32_t)(Q * 64 * storage_bytes(d->storage));
+    k.bufbytes = (uint32_t)(d->P / 64 * k.tbytes);
     k.nx = d->nx;
     k.ny = d->ny;
     k.nz = d->nz;
@@ -228,12 +229,31 @@ KDomain kdomain(const lbm_domain *d)
 
 uint32_t grid8(uint64_t blocks) { return (uint32_t)((blocks + 7) / 8 * 8); }
 
+// Grid of the single-domain kernel: one wave per tile, or at most
+// LBM_GRID_BLOCKS_PER_CU resident blocks per compute unit looping over
+// the tiles when that constant is set.
+#ifndef LBM_GRID_BLOCKS_PER_CU
+#define LBM_GRID_BLOCKS_PER_CU 0
+#endif
+
+uint32_t step_grid(const lbm_domain *d)
+{
+    uint64_t blocks = (d->ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (LBM_GRID_BLOCKS_PER_CU > 0) {
+        static int cus = 0;
+        if (!cus && (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d->device) != hipSuccess ||
+                     cus <= 0))
+            cus = 256;
+        blocks = std::min<uint64_t>(blocks, (uint64_t)cus * LBM_GRID_BLOCKS_PER_CU);
+    }
+    return grid8(blocks);
+}
+
 template <int ST, bool H>
 hipError_t launch_step_t(const lbm_domain *d, uint32_t src)
 {
     const KDomain k = kdomain(d);
-    const uint32_t blocks = grid8((d->ntiles + 3) / 4);
-    hipLaunchKernelGGL((k_stream_collide<ST, H>), dim3(blocks), dim3(256), 0, d->stream, k, d->d_tiles,
+    hipLaunchKernelGGL((k_stream_collide<ST, H>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
                        (uint32_t)d->ntiles, src);
     return hipGetLastError();
 }
@@ -323,6 +343,9 @@ int init_eq(lbm_domain *d, const float *rho_dev, const float *u_dev)
     return LBM_OK;
 }
 
+// Cells rounded up to whole 64-cell tiles.
+uint64_t plane_stride(uint64_t ncells) { return (ncells + 63) / 64 * 64; }
+
 int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage, void *hip_stream, void *fa,
            void *fb, lbm_domain **out)
 {
@@ -338,7 +361,7 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     if (periodic > 7u)
         return fail(LBM_ERR_ARG, "bad periodic mask %u", periodic);
     const uint64_t ncells = (uint64_t)nx * ny * nz;
-    const uint64_t P = (ncells + 63) / 64 * 64;
+    const uint64_t P = plane_stride(ncells);
     const uint64_t bufbytes = (uint64_t)Q * P * storage_bytes(storage);
     if (bufbytes >= (1ull << 32))
         return fail(LBM_ERR_ARG, "domain of %llu cells needs %llu bytes per buffer; the limit is 4 GiB",
@@ -455,6 +478,13 @@ extern "C" {
 const char *lbm_last_error(void) { return g_err.c_str(); }
 
 const char *lbm_version(void) { return "lbm-d3q27-chm gfx950 0.1"; }
+
+uint64_t lbm_plane_stride(int nx, int ny, int nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 65535 || ny > 65535 || nz > 65535)
+        return 0;
+    return plane_stride((uint64_t)nx * ny * nz);
+}
 
 int lbm_create_domain(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
                       void *hip_stream, lbm_domain **out)

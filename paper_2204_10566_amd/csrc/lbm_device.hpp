@@ -22,6 +22,21 @@ constexpr float kFp16Scale = 16384.0f; // 2^14: keeps f - w out of FP16 subnorma
 constexpr float kFp16InvScale = 1.0f / 16384.0f;
 
 enum : int { ST_FP32 = 0, ST_FP16S = 1, ST_BF16S = 2 };
+
+// Launch shape and cache policy of the stream-collide kernels (tuned on
+// MI355X; see the profiles).  Cache-policy bits of buffer instructions on
+// gfx950: 1 sc0, 2 nt, 16 sc1.
+#ifndef LBM_WAVES_PER_BLOCK
+#define LBM_WAVES_PER_BLOCK 4
+#endif
+#ifndef LBM_LOAD_AUX
+#define LBM_LOAD_AUX 0
+#endif
+#ifndef LBM_STORE_AUX
+#define LBM_STORE_AUX 0
+#endif
+constexpr uint32_t kWavesPerBlock = LBM_WAVES_PER_BLOCK;
+constexpr uint32_t kBlock = 64 * kWavesPerBlock;
 enum : uint8_t { FL_FLUID = 0, FL_SOLID = 1, FL_INLET = 2, FL_OUTLET = 3 };
 
 // wall-tile link mask: bits 0..26 halfway bounce-back for direction i,
@@ -65,8 +80,9 @@ struct KDomain {
     const uint32_t *inlet;   // inlet-link masks (bits 0..26), same indexing
     const float *uin;        // inlet velocity [3][P] or null
     uint32_t *status;        // bit 0: a step went unstable
-    uint32_t P;              // plane stride (elements), multiple of 64
-    uint32_t pbytes;         // plane stride in bytes
+    uint32_t P;              // cells rounded up to whole tiles (uin plane stride)
+    uint32_t tbytes;         // bytes of one tile block: 27 x 64 populations
+    uint32_t bufbytes;       // bytes of one population buffer: (P / 64) tile blocks
     uint32_t nx, ny, nz, ncells;
     FastDiv dnx, dny;
     uint32_t periodic;
@@ -88,6 +104,17 @@ struct BatchTileRec {
     uint32_t pad;
 };
 
+// Tile-major population layout: the 27 populations of the 64 cells of a
+// tile are one contiguous block, population i of the cell in lane l at
+// byte tile * tbytes + (64 i + l) * es.  A wave writes one contiguous
+// block, and reads each neighbouring row's three populations that share
+// (cy, cz) as one contiguous run, which keeps HBM accesses long.
+template <uint32_t ES> __device__ __forceinline__ uint32_t cell_bytes(uint32_t cell, uint32_t tbytes)
+{
+    return __umul24(cell >> 6, tbytes) + (cell & 63u) * ES;
+}
+template <uint32_t ES> constexpr uint32_t pop_bytes(int i) { return (uint32_t)i * 64u * ES; }
+
 // Raw buffer resource over a population buffer (gfx9-family word 3).  Loads
 // and stores go through buffer instructions: an SGPR resource, a 32-bit
 // per-lane byte offset and a per-direction SGPR byte offset; a read past the
@@ -103,11 +130,11 @@ template <> struct Storage<ST_FP32> {
     static constexpr uint32_t bytes = 4;
     __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, int)
     {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LBM_LOAD_AUX));
     }
     __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v, int)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, LBM_STORE_AUX);
     }
     __device__ static float to_f(T v, int) { return v; }
     __device__ static T from_f(float v, int) { return v; }
@@ -117,12 +144,12 @@ template <> struct Storage<ST_FP16S> {
     static constexpr uint32_t bytes = 2;
     __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, int i)
     {
-        const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+        const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LOAD_AUX);
         return to_f(__builtin_bit_cast(_Float16, h), i);
     }
     __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v, int i)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, from_f(v, i)), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, from_f(v, i)), r, voff, soff, LBM_STORE_AUX);
     }
     __device__ static float to_f(T h, int i) { return __builtin_fmaf((float)h, kFp16InvScale, weight(i)); }
     // conversion to FP16 rounds to nearest even (v_cvt_f16_f32)
@@ -133,11 +160,11 @@ template <> struct Storage<ST_BF16S> {
     static constexpr uint32_t bytes = 2;
     __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, int i)
     {
-        return to_f(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0), i);
+        return to_f(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LOAD_AUX), i);
     }
     __device__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v, int i)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(from_f(v, i), r, voff, soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(from_f(v, i), r, voff, soff, LBM_STORE_AUX);
     }
     __device__ static float to_f(T h, int i) { return __uint_as_float((uint32_t)h << 16) + weight(i); }
     // round to nearest even on the upper 16 bits (finite inputs)
@@ -277,8 +304,8 @@ __device__ __forceinline__ void update_tile(const KDomain &d, uint32_t tile, int
 {
     using S = Storage<ST>;
     constexpr uint32_t es = S::bytes;
-    const auto rs = make_rsrc(d.buf[src_idx], Q * d.pbytes);
-    const auto rd = make_rsrc(d.buf[src_idx ^ 1u], Q * d.pbytes);
+    const auto rs = make_rsrc(d.buf[src_idx], d.bufbytes);
+    const auto rd = make_rsrc(d.buf[src_idx ^ 1u], d.bufbytes);
     const uint32_t lin = tile * 64u + lane;
     uint32_t m = 0;
     if (mslot >= 0)
@@ -305,28 +332,26 @@ __device__ __forceinline__ void update_tile(const KDomain &d, uint32_t tile, int
     sz[1] = z;
     sz[0] = (z + 1 < d.nz) ? z + 1 : (pz ? 0u : z);
     sz[2] = (z > 0) ? z - 1 : (pz ? d.nz - 1 : 0u);
-    // byte offsets of the source rows and columns within one plane
-    uint32_t rowb[9], colb[3];
+    // first cell of each source row (cy, cz)
+    uint32_t row[9];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            rowb[b + 3 * c] = (sz[c] * d.ny + sy[b]) * d.nx * es;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-        colb[a] = sx[a] * es;
+            row[b + 3 * c] = (sz[c] * d.ny + sy[b]) * d.nx;
 
     float f[Q];
     if (mslot < 0) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            f[i] = S::load(rs, rowb[i / 3] + colb[i % 3], (uint32_t)i * d.pbytes, i);
+            f[i] = S::load(rs, cell_bytes<es>(row[i / 3] + sx[i % 3], d.tbytes), pop_bytes<es>(i), i);
     } else {
         // bounce-back links read the opposite population of the cell itself
+        const uint32_t self = cell_bytes<es>(lin, d.tbytes);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const uint32_t off = (m & (1u << i)) ? (uint32_t)(Q - 1 - i) * d.pbytes + lin * es
-                                                 : (uint32_t)i * d.pbytes + rowb[i / 3] + colb[i % 3];
+            const uint32_t off = (m & (1u << i)) ? self + pop_bytes<es>(Q - 1 - i)
+                                                 : cell_bytes<es>(row[i / 3] + sx[i % 3], d.tbytes) + pop_bytes<es>(i);
             f[i] = S::load(rs, off, 0u, i);
         }
         if ((m & kMaskInlet) && d.uin) { // without an inlet velocity the inlet is a resting wall
@@ -350,9 +375,10 @@ __device__ __forceinline__ void update_tile(const KDomain &d, uint32_t tile, int
     if (!(rho > 0.f) || !(__builtin_fabsf(ux) + __builtin_fabsf(uy) + __builtin_fabsf(uz) < 1e30f))
         atomicOr(d.status, 1u);
 
+    const uint32_t own = cell_bytes<es>(lin, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        S::store(rd, lin * es, (uint32_t)i * d.pbytes, f[i], i);
+        S::store(rd, own, pop_bytes<es>(i), f[i], i);
 }
 
 // Block index -> logical block: consecutive hardware blocks go round-robin
@@ -361,30 +387,36 @@ __device__ __forceinline__ void update_tile(const KDomain &d, uint32_t tile, int
 // of 8.
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) { return (b & 7u) * (G >> 3) + (b >> 3); }
 
+// Single-domain step.  Each wave takes whole tiles, walking the tile list
+// with a stride of the grid's wave count (one pass when the grid covers
+// every tile).
 template <int ST, bool HIGH1>
-__global__ __launch_bounds__(256) void k_stream_collide(KDomain d, const TileRec *__restrict__ tiles, uint32_t ntiles,
-                                                        uint32_t src_idx)
+__global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const TileRec *__restrict__ tiles,
+                                                           uint32_t ntiles, uint32_t src_idx)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t t = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6));
-    if (t >= ntiles)
-        return;
-    const TileRec rec = tiles[t];
-    update_tile<ST, HIGH1>(d, rec.tile, rec.mask, src_idx, lane);
+    const uint32_t nw = gridDim.x * kWavesPerBlock;
+    const uint32_t w0 =
+        __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    for (uint32_t t = w0; t < ntiles; t += nw) {
+        const TileRec rec = tiles[t];
+        update_tile<ST, HIGH1>(d, rec.tile, rec.mask, src_idx, lane);
+    }
 }
 
 // Packed multi-domain step.  ctrl[0] = number of tile records, ctrl[1] =
 // global step.  A persistent grid walks the table; each wave takes whole
 // tiles, each tile belongs to one domain.
 template <int ST, bool HIGH1>
-__global__ __launch_bounds__(256) void k_stream_collide_batched(const KDomain *__restrict__ doms,
+__global__ __launch_bounds__(kBlock) void k_stream_collide_batched(const KDomain *__restrict__ doms,
                                                                 const BatchTileRec *__restrict__ tiles,
                                                                 const uint32_t *__restrict__ ctrl)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t ntiles = ctrl[0], g = ctrl[1];
-    const uint32_t nw = gridDim.x * 4u;
-    const uint32_t w0 = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6));
+    const uint32_t nw = gridDim.x * kWavesPerBlock;
+    const uint32_t w0 =
+        __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
     for (uint32_t t = w0; t < ntiles; t += nw) {
         const BatchTileRec rec = tiles[t];
         const KDomain &dd = doms[rec.slot];
@@ -437,12 +469,17 @@ __global__ __launch_bounds__(256) void k_init_eq(KDomain d, const uint8_t *__res
         phi[a][1] = 2.0f / 3.0f - w2;
         phi[a][2] = (1.f + 3.f * w + 3.f * w2) * (1.0f / 6.0f);
     }
+    const uint32_t cb = cell_bytes<es>(c, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float fe = upd ? r * phi[0][i % 3] * phi[1][(i / 3) % 3] * phi[2][i / 9] : weight(i);
-        typename S::T val = S::from_f(fe, i);
-        *(typename S::T *)(d.buf[dst_idx] + (size_t)i * d.pbytes + c * es) = val;
+        *(typename S::T *)(d.buf[dst_idx] + cb + pop_bytes<es>(i)) = S::from_f(fe, i);
     }
+}
+
+template <int ST> __device__ __forceinline__ const typename Storage<ST>::T *pop_at(const char *buf, uint32_t cb, int i)
+{
+    return (const typename Storage<ST>::T *)(buf + cb + pop_bytes<Storage<ST>::bytes>(i));
 }
 
 // Density and velocity of the stored state at updated cells.
@@ -456,10 +493,10 @@ __global__ __launch_bounds__(256) void k_moments(KDomain d, const uint8_t *__res
         return;
     float r = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
     if (flags[c] == FL_FLUID || flags[c] == FL_OUTLET) {
-        const typename S::T *base = (const typename S::T *)d.buf[cur];
+        const uint32_t cb = cell_bytes<S::bytes>(c, d.tbytes);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float fi = S::to_f(base[(size_t)i * d.P + c], i);
+            const float fi = S::to_f(*pop_at<ST>(d.buf[cur], cb, i), i);
             r += fi;
             jx += (float)cx(i) * fi;
             jy += (float)cy(i) * fi;
@@ -484,10 +521,10 @@ __global__ __launch_bounds__(256) void k_export(KDomain d, uint32_t cur, float *
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.ncells)
         return;
-    const typename S::T *base = (const typename S::T *)d.buf[cur];
+    const uint32_t cb = cell_bytes<S::bytes>(c, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        out[(size_t)i * d.ncells + c] = S::to_f(base[(size_t)i * d.P + c], i);
+        out[(size_t)i * d.ncells + c] = S::to_f(*pop_at<ST>(d.buf[cur], cb, i), i);
 }
 
 template <int ST>
@@ -497,10 +534,10 @@ __global__ __launch_bounds__(256) void k_import(KDomain d, uint32_t cur, const f
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.ncells)
         return;
-    typename S::T *base = (typename S::T *)d.buf[cur];
+    const uint32_t cb = cell_bytes<S::bytes>(c, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        base[(size_t)i * d.P + c] = S::from_f(in[(size_t)i * d.ncells + c], i);
+        *(typename S::T *)(d.buf[cur] + cb + pop_bytes<S::bytes>(i)) = S::from_f(in[(size_t)i * d.ncells + c], i);
 }
 
 } // namespace lbm

@@ -242,7 +242,8 @@ def test_adopted_torch_buffers_and_stream(capi, orc):
     n = 16
     fl = I.periodic_box(n)
     u0 = I.taylor_green_velocity(n, n, n, 0.03).astype(np.float32)
-    P = (fl.size + 63) // 64 * 64
+    P = int(capi.lbm_plane_stride(n, n, n))
+    assert P >= fl.size and P % 64 == 0
     a = torch.empty(27 * P, dtype=torch.float32, device="cuda")
     b = torch.empty(27 * P, dtype=torch.float32, device="cuda")
     s = torch.cuda.Stream()
