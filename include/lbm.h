@@ -90,6 +90,7 @@ typedef struct lbm_domain_info {
     uint64_t n_updated;     /* fluid + outlet cells: the cells one step updates */
     uint64_t n_tiles;       /* 64-cell tiles holding at least one updated cell */
     uint64_t n_wall_tiles;  /* of those, tiles with a non-plain link or a non-updated cell */
+    uint64_t n_inlet;       /* inlet cells */
     uint64_t device_bytes;  /* device memory held by the domain */
     uint64_t bytes_per_cell_update; /* algorithmic HBM bytes per updated cell: 2*27*sizeof(storage) */
 } lbm_domain_info;
@@ -149,9 +150,15 @@ int lbm_set_rates(lbm_domain *d, double omega, double omega_bulk, double omega_h
  *   u_in  host, 3*ncells floats, layout [component][cell]; read only at
  *         LBM_INLET cells.  A link from an inlet cell s into a fluid cell x
  *         gives f_i(x) = f*_opp(i)(x) + 6 w_i (c_i . u_in(s)) (wall density 1).
- * Without a call, inlet cells act as resting walls.
+ * Without a call, inlet cells act as resting walls.  Only the inlet cells'
+ * values are kept (3 floats per inlet cell on the device).
  */
 int lbm_set_inlet(lbm_domain *d, const float *u_in);
+
+/* As lbm_set_inlet with the values of the inlet cells only: u_inlet is
+ * host, 3*n_inlet floats, layout [component][k] for the k-th inlet cell in
+ * ascending cell order (n_inlet from lbm_domain_get_info). */
+int lbm_set_inlet_cells(lbm_domain *d, const float *u_inlet);
 
 /*
  * Set the state to the equilibrium f^eq(rho, u) (Eq. (4), sixth order) at
@@ -185,7 +192,8 @@ int lbm_get_moments_device(lbm_domain *d, float *rho_dev, float *u_dev);
  * The stored populations f_i as FP32 (shifted storage is converted back:
  * f_i = w_i + stored/scale).
  *   f  host, 27*ncells floats, layout [i][cell].
- * Values at cells that are not updated are unspecified.
+ * Cells that are not updated keep the values of the last lbm_init_fields
+ * or lbm_set_populations (the lattice weights after creation).
  */
 int lbm_get_populations(lbm_domain *d, float *f);
 
@@ -242,8 +250,11 @@ int lbm_batch_poll(lbm_batch *b, int wait, int *done_slots, int max, int *n_done
  * LBM_ERR_UNSTABLE if any of its batched steps was unstable). */
 int lbm_batch_release(lbm_batch *b, int slot, lbm_domain **d);
 
-/* Number of resident slots, the step counter and the budget in use. */
-int lbm_batch_stats(const lbm_batch *b, int *resident, uint64_t *steps_enqueued, size_t *bytes_in_use);
+/* Number of resident slots, packed steps enqueued so far, packed steps
+ * known complete on the device (as of the last poll), and the budget in
+ * use.  Any output pointer may be NULL. */
+int lbm_batch_stats(const lbm_batch *b, int *resident, uint64_t *steps_enqueued, uint64_t *steps_done,
+                    size_t *bytes_in_use);
 
 int lbm_batch_destroy(lbm_batch *b);
 

@@ -34,7 +34,7 @@ class DomainInfo(ctypes.Structure):
         ("storage", ctypes.c_int), ("periodic", ctypes.c_uint),
         ("ncells", ctypes.c_uint64), ("plane_stride", ctypes.c_uint64),
         ("n_updated", ctypes.c_uint64), ("n_tiles", ctypes.c_uint64),
-        ("n_wall_tiles", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+        ("n_wall_tiles", ctypes.c_uint64), ("n_inlet", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
         ("bytes_per_cell_update", ctypes.c_uint64),
     ]
 
@@ -53,6 +53,7 @@ SIGNATURES = {
     "lbm_set_params": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_rates": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_inlet": (ctypes.c_int, [_vp, _fp]),
+    "lbm_set_inlet_cells": (ctypes.c_int, [_vp, _fp]),
     "lbm_init_fields": (ctypes.c_int, [_vp, _fp, _fp]),
     "lbm_step": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lbm_get_moments": (ctypes.c_int, [_vp, _fp, _fp]),
@@ -67,7 +68,8 @@ SIGNATURES = {
     "lbm_batch_step": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lbm_batch_poll": (ctypes.c_int, [_vp, ctypes.c_int, _ip, ctypes.c_int, _ip]),
     "lbm_batch_release": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
-    "lbm_batch_stats": (ctypes.c_int, [_vp, _ip, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_batch_stats": (ctypes.c_int, [_vp, _ip, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_size_t)]),
     "lbm_batch_destroy": (ctypes.c_int, [_vp]),
     "lbm_plane_stride": (ctypes.c_uint64, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbm_selftest_host": (ctypes.c_int, []),
@@ -150,6 +152,11 @@ class Domain:
         a, p = _f32(uin, 3 * self.ncells)
         check(lbm_set_inlet(self.h, p))
 
+    def set_inlet_cells(self, u_inlet):
+        """u_inlet: [3, n_inlet], inlet cells in ascending cell order."""
+        a, p = _f32(u_inlet, 3 * int(self.info().n_inlet))
+        check(lbm_set_inlet_cells(self.h, p))
+
     def init_fields(self, rho=None, u=None):
         ra, rp = _f32(rho, self.ncells)
         ua, up = _f32(u, 3 * self.ncells)
@@ -224,11 +231,13 @@ class Batch:
         check(lbm_batch_release(self.h, int(slot), ctypes.byref(d)))
 
     def stats(self):
+        """(resident slots, steps enqueued, steps done, bytes in use)."""
         r = ctypes.c_int()
         s = ctypes.c_uint64()
+        dn = ctypes.c_uint64()
         b = ctypes.c_size_t()
-        check(lbm_batch_stats(self.h, ctypes.byref(r), ctypes.byref(s), ctypes.byref(b)))
-        return r.value, s.value, b.value
+        check(lbm_batch_stats(self.h, ctypes.byref(r), ctypes.byref(s), ctypes.byref(dn), ctypes.byref(b)))
+        return r.value, s.value, dn.value, b.value
 
     def destroy(self):
         if self.h:

@@ -67,9 +67,10 @@ bool updated(uint8_t fl) { return fl == LBM_FLUID || fl == LBM_OUTLET; }
 // Link classification of one cell (host copy of the boundary rules):
 // returns the wall mask (bit i: halfway bounce-back for population i,
 // kMaskInlet if any link comes from an inlet cell, kMaskSkip if the cell is
-// not updated) and the inlet mask.
+// not updated) and the inlet mask; src[i] receives the inlet cell of each
+// inlet link.
 void classify_cell(const uint8_t *flags, int nx, int ny, int nz, unsigned per, uint64_t cell, uint32_t &wall,
-                   uint32_t &inl)
+                   uint32_t &inl, uint64_t *src = nullptr)
 {
     wall = 0;
     inl = 0;
@@ -93,25 +94,35 @@ void classify_cell(const uint8_t *flags, int nx, int ny, int nz, unsigned per, u
             wall |= 1u << i;
             continue;
         }
-        const uint8_t fs = flags[((uint64_t)sz * ny + sy) * nx + sx];
+        const uint64_t s = ((uint64_t)sz * ny + sy) * nx + sx;
+        const uint8_t fs = flags[s];
         if (fs == LBM_SOLID) {
             wall |= 1u << i;
         } else if (fs == LBM_INLET) {
             wall |= (1u << i) | kMaskInlet;
             inl |= 1u << i;
+            if (src)
+                src[i] = s;
         }
     }
 }
 
+// Tile list of a domain.  wall: per cell of each wall tile the link mask;
+// inlet: per cell of each wall tile the index of its inlet record (kNoRec
+// if it has no inlet link); inlrec: per record the inlet link mask and 27
+// inlet ordinals (the rank of the link's inlet cell among all inlet cells,
+// kNoRec for other links).
 struct Tiles {
     std::vector<TileRec> recs;
-    std::vector<uint32_t> wall, inlet;
+    std::vector<uint32_t> wall, inlet, inlrec;
     uint64_t n_updated = 0;
 };
 
 // Build the tile list in tile order.  Work is split over host threads by
-// contiguous tile ranges and concatenated in order.
-void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, Tiles &out)
+// contiguous tile ranges and concatenated in order.  inlet_cells: the inlet
+// cells in ascending order (their position is the inlet ordinal).
+void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, const std::vector<uint64_t> &inlet_cells,
+                 Tiles &out)
 {
     const uint64_t ncells = (uint64_t)nx * ny * nz;
     const uint64_t ntiles = (ncells + 63) / 64;
@@ -122,16 +133,29 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, Til
     auto work = [&](unsigned p) {
         const uint64_t t0 = ntiles * p / nth, t1 = ntiles * (p + 1) / nth;
         Tiles &T = part[p];
-        uint32_t wl[64], il[64];
+        uint32_t wl[64], il[64], rec[64];
+        uint64_t src[Q];
         for (uint64_t t = t0; t < t1; ++t) {
             bool any = false, plain = true;
             for (int l = 0; l < 64; ++l) {
                 const uint64_t c = t * 64 + l;
+                rec[l] = kNoRec;
                 if (c >= ncells) {
                     wl[l] = kMaskSkip;
                     il[l] = 0;
                 } else {
-                    classify_cell(flags, nx, ny, nz, per, c, wl[l], il[l]);
+                    classify_cell(flags, nx, ny, nz, per, c, wl[l], il[l], src);
+                }
+                if (il[l]) {
+                    rec[l] = (uint32_t)(T.inlrec.size() / kRecWords);
+                    T.inlrec.push_back(il[l]);
+                    for (int i = 0; i < Q; ++i) {
+                        uint32_t ord = kNoRec;
+                        if (il[l] & (1u << i))
+                            ord = (uint32_t)(std::lower_bound(inlet_cells.begin(), inlet_cells.end(), src[i]) -
+                                             inlet_cells.begin());
+                        T.inlrec.push_back(ord);
+                    }
                 }
                 if (!(wl[l] & kMaskSkip)) {
                     any = true;
@@ -147,7 +171,7 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, Til
             } else {
                 T.recs.push_back({(uint32_t)t, (int32_t)(T.wall.size() / 64)});
                 T.wall.insert(T.wall.end(), wl, wl + 64);
-                T.inlet.insert(T.inlet.end(), il, il + 64);
+                T.inlet.insert(T.inlet.end(), rec, rec + 64);
             }
         }
     };
@@ -159,13 +183,16 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, Til
         t.join();
     for (unsigned p = 0; p < nth; ++p) {
         const int32_t off = (int32_t)(out.wall.size() / 64);
+        const uint32_t roff = (uint32_t)(out.inlrec.size() / kRecWords);
         for (TileRec r : part[p].recs) {
             if (r.mask >= 0)
                 r.mask += off;
             out.recs.push_back(r);
         }
         out.wall.insert(out.wall.end(), part[p].wall.begin(), part[p].wall.end());
-        out.inlet.insert(out.inlet.end(), part[p].inlet.begin(), part[p].inlet.end());
+        for (uint32_t r : part[p].inlet)
+            out.inlet.push_back(r == kNoRec ? kNoRec : r + roff);
+        out.inlrec.insert(out.inlrec.end(), part[p].inlrec.begin(), part[p].inlrec.end());
         out.n_updated += part[p].n_updated;
     }
 }
@@ -186,8 +213,9 @@ struct lbm_domain {
     int cur = 0; // buffer holding the current state
     uint8_t *d_flags = nullptr;
     TileRec *d_tiles = nullptr;
-    uint32_t *d_wall = nullptr, *d_inlet = nullptr;
-    float *d_uin = nullptr;
+    uint32_t *d_wall = nullptr, *d_inlet = nullptr, *d_inlrec = nullptr;
+    float *d_uin = nullptr;                // [3][n_inlet]
+    std::vector<uint64_t> inlet_cells;     // inlet cells, ascending (index = inlet ordinal)
     uint32_t *d_status = nullptr;
     uint64_t ntiles = 0, nwall = 0, n_updated = 0;
     double omega = 1.0, omega_b = 1.0, omega_h = 1.0;
@@ -209,7 +237,9 @@ KDomain kdomain(const lbm_domain *d)
     k.buf[1] = d->buf[1];
     k.wall = d->d_wall;
     k.inlet = d->d_inlet;
+    k.inlrec = d->d_inlrec;
     k.uin = d->d_uin;
+    k.n_inlet = (uint32_t)d->inlet_cells.size();
     k.status = d->d_status;
     k.P = (uint32_t)d->P;
     k.tbytes = (uint32_t)(Q * 64 * storage_bytes(d->storage));
@@ -322,6 +352,7 @@ void free_domain(lbm_domain *d)
     (void)hipFree(d->d_tiles);
     (void)hipFree(d->d_wall);
     (void)hipFree(d->d_inlet);
+    (void)hipFree(d->d_inlrec);
     (void)hipFree(d->d_uin);
     (void)hipFree(d->d_status);
     if (d->own_stream && d->stream)
@@ -329,14 +360,17 @@ void free_domain(lbm_domain *d)
     delete d;
 }
 
+// Both buffers receive the initial state, so that cells no step updates
+// (walls, inlet cells, tile padding) hold defined values in either buffer.
 int init_eq(lbm_domain *d, const float *rho_dev, const float *u_dev)
 {
     const KDomain k = kdomain(d);
     const uint32_t blocks = (uint32_t)((d->P + 255) / 256);
-    dispatch_storage(d->storage, [&](auto st) {
-        hipLaunchKernelGGL((k_init_eq<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, d->d_flags,
-                           rho_dev, u_dev, (uint32_t)d->cur);
-    });
+    for (uint32_t b = 0; b < 2; ++b)
+        dispatch_storage(d->storage, [&](auto st) {
+            hipLaunchKernelGGL((k_init_eq<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k,
+                               d->d_flags, rho_dev, u_dev, b);
+        });
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemsetAsync(d->d_status, 0, sizeof(uint32_t), d->stream));
     d->unstable = false;
@@ -366,6 +400,7 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     if (bufbytes >= (1ull << 32))
         return fail(LBM_ERR_ARG, "domain of %llu cells needs %llu bytes per buffer; the limit is 4 GiB",
                     (unsigned long long)ncells, (unsigned long long)bufbytes);
+    std::vector<uint64_t> inlet_cells;
     for (uint64_t c = 0; c < ncells; ++c) {
         const uint8_t f = flags[c];
         if (f > LBM_OUTLET)
@@ -373,9 +408,11 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
         if (f == LBM_OUTLET && ((c % nx) != (uint64_t)nx - 1 || (periodic & 1u)))
             return fail(LBM_ERR_ARG, "outlet cell %llu not on the last x plane of a non-periodic x axis",
                         (unsigned long long)c);
+        if (f == LBM_INLET)
+            inlet_cells.push_back(c);
     }
     Tiles T;
-    build_tiles(flags, nx, ny, nz, periodic, T);
+    build_tiles(flags, nx, ny, nz, periodic, inlet_cells, T);
 
     lbm_domain *d = new lbm_domain();
     d->nx = nx;
@@ -389,6 +426,7 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     d->nwall = T.wall.size() / 64;
     d->n_updated = T.n_updated;
     d->h_tiles = T.recs;
+    d->inlet_cells = std::move(inlet_cells);
     auto bail = [&](int code) {
         free_domain(d);
         return code;
@@ -426,14 +464,12 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     }
     if (!dmalloc((void **)&d->d_flags, ncells) || !dmalloc((void **)&d->d_tiles, T.recs.size() * sizeof(TileRec)) ||
         !dmalloc((void **)&d->d_wall, T.wall.size() * 4) || !dmalloc((void **)&d->d_inlet, T.inlet.size() * 4) ||
-        !dmalloc((void **)&d->d_status, sizeof(uint32_t)))
+        !dmalloc((void **)&d->d_inlrec, T.inlrec.size() * 4) || !dmalloc((void **)&d->d_status, sizeof(uint32_t)))
         return bail(fail(LBM_ERR_OOM, "domain tables"));
-    if (hipMemcpy(d->d_flags, flags, ncells, hipMemcpyHostToDevice) != hipSuccess ||
-        (d->ntiles && hipMemcpy(d->d_tiles, T.recs.data(), T.recs.size() * sizeof(TileRec),
-                                hipMemcpyHostToDevice) != hipSuccess) ||
-        (d->nwall && (hipMemcpy(d->d_wall, T.wall.data(), T.wall.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-                      hipMemcpy(d->d_inlet, T.inlet.data(), T.inlet.size() * 4, hipMemcpyHostToDevice) !=
-                          hipSuccess)))
+    auto up = [](void *dst, const void *src, size_t n) { return n == 0 || hipMemcpy(dst, src, n, hipMemcpyHostToDevice) == hipSuccess; };
+    if (!up(d->d_flags, flags, ncells) || !up(d->d_tiles, T.recs.data(), T.recs.size() * sizeof(TileRec)) ||
+        !up(d->d_wall, T.wall.data(), T.wall.size() * 4) || !up(d->d_inlet, T.inlet.data(), T.inlet.size() * 4) ||
+        !up(d->d_inlrec, T.inlrec.data(), T.inlrec.size() * 4))
         return bail(fail(LBM_ERR_DEVICE, "upload of domain tables failed"));
     d->omega = d->omega_b = 1.0 / 0.6;
     d->omega_h = 1.0;
@@ -529,27 +565,42 @@ int lbm_set_params(lbm_domain *d, double tau, double omega_bulk, double omega_hi
     return lbm_set_rates(d, 1.0 / tau, omega_bulk, omega_high);
 }
 
+int lbm_set_inlet_cells(lbm_domain *d, const float *u_inlet)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!u_inlet)
+        return fail(LBM_ERR_ARG, "u_inlet is null");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    const size_t n = d->inlet_cells.size();
+    if (n == 0)
+        return LBM_OK;
+    if (!d->d_uin) {
+        if (hipMalloc((void **)&d->d_uin, 3 * n * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            d->d_uin = nullptr;
+            return fail(LBM_ERR_OOM, "inlet velocity buffer");
+        }
+        d->device_bytes += 3 * n * sizeof(float);
+        d->graph_dirty = true;
+    }
+    HIP_TRY(hipMemcpy(d->d_uin, u_inlet, 3 * n * sizeof(float), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
 int lbm_set_inlet(lbm_domain *d, const float *u_in)
 {
     if (int rc = check_domain(d))
         return rc;
     if (!u_in)
         return fail(LBM_ERR_ARG, "u_in is null");
-    if (d->batch)
-        return fail(LBM_ERR_STATE, "domain is resident in a batch");
-    if (!d->d_uin) {
-        if (hipMalloc((void **)&d->d_uin, 3 * d->P * sizeof(float)) != hipSuccess) {
-            (void)hipGetLastError();
-            d->d_uin = nullptr;
-            return fail(LBM_ERR_OOM, "inlet velocity buffer");
-        }
-        d->device_bytes += 3 * d->P * sizeof(float);
-        d->graph_dirty = true;
-    }
+    const size_t n = d->inlet_cells.size();
+    std::vector<float> compact(3 * n);
     for (int a = 0; a < 3; ++a)
-        HIP_TRY(hipMemcpy(d->d_uin + a * d->P, u_in + a * d->ncells, d->ncells * sizeof(float),
-                          hipMemcpyHostToDevice));
-    return LBM_OK;
+        for (size_t k = 0; k < n; ++k)
+            compact[a * n + k] = u_in[a * d->ncells + d->inlet_cells[k]];
+    return lbm_set_inlet_cells(d, compact.data());
 }
 
 int lbm_init_fields(lbm_domain *d, const float *rho, const float *u)
@@ -695,10 +746,10 @@ int lbm_set_populations(lbm_domain *d, const float *f)
     if (rc == LBM_OK) {
         const KDomain k = kdomain(d);
         const uint32_t blocks = (uint32_t)((d->ncells + 255) / 256);
-        dispatch_storage(d->storage, [&](auto st) {
-            hipLaunchKernelGGL((k_import<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k,
-                               (uint32_t)d->cur, df);
-        });
+        for (uint32_t b = 0; b < 2; ++b) // both buffers, as for initialisation
+            dispatch_storage(d->storage, [&](auto st) {
+                hipLaunchKernelGGL((k_import<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, b, df);
+            });
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(d->stream) != hipSuccess)
             rc = fail(LBM_ERR_DEVICE, "population import failed");
     }
@@ -720,6 +771,7 @@ int lbm_domain_get_info(const lbm_domain *d, lbm_domain_info *info)
     info->n_updated = d->n_updated;
     info->n_tiles = d->ntiles;
     info->n_wall_tiles = d->nwall;
+    info->n_inlet = d->inlet_cells.size();
     info->device_bytes = d->device_bytes;
     info->bytes_per_cell_update = 2ull * Q * storage_bytes(d->storage);
     return LBM_OK;

@@ -44,6 +44,10 @@ enum : uint8_t { FL_FLUID = 0, FL_SOLID = 1, FL_INLET = 2, FL_OUTLET = 3 };
 // the cell is not updated.
 constexpr uint32_t kMaskInlet = 1u << 30;
 constexpr uint32_t kMaskSkip = 1u << 31;
+// inlet record of a cell with moving-wall inlet links: word 0 the link mask,
+// word 1 + i the ordinal of the inlet cell that link i comes from
+constexpr uint32_t kRecWords = 28;
+constexpr uint32_t kNoRec = 0xffffffffu;
 
 // D3Q27 weights, product of the 1-D weights 2/3 (c = 0) and 1/6 (c = +-1)
 // (App. A, Eqs. (A.1)-(A.2)); index i = (cx+1) + 3(cy+1) + 9(cz+1).
@@ -77,8 +81,10 @@ __host__ __device__ inline uint32_t fdiv(uint32_t n, FastDiv f)
 struct KDomain {
     char *buf[2];            // population buffers, 27 planes of P elements
     const uint32_t *wall;    // link masks of wall tiles, 64 per wall tile
-    const uint32_t *inlet;   // inlet-link masks (bits 0..26), same indexing
-    const float *uin;        // inlet velocity [3][P] or null
+    const uint32_t *inlet;   // inlet record index per wall-tile cell, same indexing
+    const uint32_t *inlrec;  // inlet records, kRecWords each
+    const float *uin;        // inlet velocity [3][n_inlet] by inlet ordinal, or null
+    uint32_t n_inlet;
     uint32_t *status;        // bit 0: a step went unstable
     uint32_t P;              // cells rounded up to whole tiles (uin plane stride)
     uint32_t tbytes;         // bytes of one tile block: 27 x 64 populations
@@ -357,13 +363,14 @@ __device__ __forceinline__ void update_tile(const KDomain &d, uint32_t tile, int
         if ((m & kMaskInlet) && d.uin) { // without an inlet velocity the inlet is a resting wall
             // moving-wall bounce-back: + 2 w_i (c_i . u_in) / theta0 with
             // wall density 1, u_in at the inlet cell the link comes from
-            const uint32_t im = d.inlet[(uint32_t)mslot * 64u + lane];
+            const uint32_t *rec = d.inlrec + d.inlet[(uint32_t)mslot * 64u + lane] * kRecWords;
+            const uint32_t im = rec[0];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 if (im & (1u << i)) {
-                    const uint32_t s = (sz[i / 9] * d.ny + sy[(i / 3) % 3]) * d.nx + sx[i % 3];
-                    const float cu = (float)cx(i) * d.uin[s] + (float)cy(i) * d.uin[d.P + s] +
-                                     (float)cz(i) * d.uin[2u * d.P + s];
+                    const uint32_t k = rec[1 + i];
+                    const float cu = (float)cx(i) * d.uin[k] + (float)cy(i) * d.uin[d.n_inlet + k] +
+                                     (float)cz(i) * d.uin[2u * d.n_inlet + k];
                     f[i] += 6.0f * weight(i) * cu;
                 }
             }

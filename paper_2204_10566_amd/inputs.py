@@ -185,6 +185,21 @@ class Nozzle:
                 uin[a, :, :, 0] += np.where(mask, noise * u0 * pert[a], 0.0)
         return uin
 
+    def inlet_velocity_cells(self, u_throat_mean: float, flags: np.ndarray | None = None) -> np.ndarray:
+        """The parabolic inlet profile on the inlet cells only: [3, n_inlet]
+        in ascending cell order (the layout of lbm_set_inlet_cells)."""
+        fl = self.flags() if flags is None else flags
+        u0 = self.mean_inlet_velocity(u_throat_mean)
+        d0 = 2.0 * self.R
+        cells = np.flatnonzero(fl.ravel() == INLET)
+        z = cells // (self.n * self.length)
+        y = (cells // self.length) % self.n
+        c = self.n / 2.0
+        r2 = (y + 0.5 - c) ** 2 + (z + 0.5 - c) ** 2
+        out = np.zeros((3, cells.size))
+        out[0] = 2.0 * u0 * (1.0 - 4.0 * r2 / d0 ** 2)
+        return out
+
     def initial_velocity(self, u_throat_mean: float) -> np.ndarray:
         """Plug flow u_x = u0 (R / R(x))^2 on fluid cells (mass consistent)."""
         u0 = self.mean_inlet_velocity(u_throat_mean)
@@ -308,13 +323,19 @@ class Request:
     steps: int
 
     def build(self):
+        """Flags, inlet velocity on the inlet cells only, and tau.  A served
+        solve starts from rest (rho = 1, u = 0)."""
         tau, u_thr = nozzle_tau(self.nozzle, self.Re)
+        fl = self.nozzle.flags()
         return {
-            "flags": self.nozzle.flags(),
-            "uin": self.nozzle.inlet_velocity(u_thr),
-            "u0": self.nozzle.initial_velocity(u_thr),
+            "flags": fl,
+            "uin_cells": self.nozzle.inlet_velocity_cells(u_thr, fl),
             "tau": tau,
         }
+
+    @property
+    def ncells(self) -> int:
+        return self.nozzle.n * self.nozzle.n * self.nozzle.length
 
 
 def serving_trace(count: int = 200, rate: float = 20.0, seed: int = 0, steps_lo: int = 1000,

@@ -1,0 +1,256 @@
+"""Continuous-batching service of many independent lattice Boltzmann solves.
+
+Requests (nozzle-like solves of different grid sizes and step counts) arrive
+over time.  Host-side preparation (voxel flags, inlet profile, domain
+creation and upload) runs on a worker pool; the serving thread admits
+prepared domains first-come-first-served while the batch's HBM budget has
+room, advances every resident domain with one packed, graph-replayed launch
+per time step, and hands finished domains back to the pool, which copies
+their density and velocity to the host.  A domain's state stays on the
+device from admission to completion.  The same trace can be served one solve
+at a time for comparison.
+
+Latency of a request = time from its arrival to its result on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import concurrent.futures as cf
+import json
+import math
+import sys
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import capi
+from . import inputs as I
+
+
+@dataclass
+class Outcome:
+    rid: int
+    arrival: float
+    admitted: float = math.nan
+    done: float = math.nan
+    status: int = 0
+    updated_cells: int = 0
+    steps: int = 0
+    rho: np.ndarray | None = field(default=None, repr=False)
+    u: np.ndarray | None = field(default=None, repr=False)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def prepare(req: I.Request, storage: str, stream=None) -> capi.Domain:
+    b = req.build()
+    d = capi.Domain(b["flags"], periodic=0, storage=storage, stream=stream)
+    d.set_params(b["tau"], 1.0 / b["tau"], 1.0)
+    d.set_inlet_cells(b["uin_cells"])
+    d.init_fields()
+    return d
+
+
+def finish(d: capi.Domain, keep_fields: bool):
+    """Copy the result to the host and free the domain.  Returns (status, rho,
+    u, updated cells); status is LBM_ERR_UNSTABLE if any step went unstable."""
+    status = d.step_status(0)
+    rho, u = d.moments()
+    info = d.info()
+    d.destroy()
+    if not keep_fields:
+        rho, u = None, None
+    return status, rho, u, int(info.n_updated)
+
+
+def percentiles(lat):
+    a = np.asarray(lat)
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def summarise(mode, outs, wall, budget=None):
+    lat = [o.latency for o in outs]
+    p50, p99 = percentiles(lat)
+    upd = sum(o.updated_cells * o.steps for o in outs if o.status == 0)
+    return {
+        "mode": mode,
+        "requests": len(outs),
+        "unstable": sum(1 for o in outs if o.status != 0),
+        "p50_s": round(p50, 4),
+        "p99_s": round(p99, 4),
+        "mean_s": round(float(np.mean(lat)), 4),
+        "makespan_s": round(wall, 3),
+        "fluid_mlups": round(upd / wall / 1e6, 1),
+        "budget_bytes": budget,
+    }
+
+
+def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8, max_ahead=2, workers=4,
+                     keep_fields=False, realtime=True):
+    """Serve a trace with continuous batching.  Returns (outcomes, summary)."""
+    import torch
+
+    if budget_bytes is None:
+        free, _ = torch.cuda.mem_get_info()
+        budget_bytes = int(min(288e9, 0.85 * free))
+    batch = capi.Batch(budget_bytes, storage)
+    pool = cf.ThreadPoolExecutor(max_workers=workers)
+    reqs = sorted(trace, key=lambda r: r.arrival)
+    outs = {r.rid: Outcome(r.rid, r.arrival, steps=r.steps) for r in reqs}
+    nxt = 0
+    preparing = collections.deque()  # (req, future) in arrival order
+    waiting = collections.deque()    # (req, domain) prepared, not yet admitted
+    resident = {}                    # slot -> (req, domain)
+    finishing = []                   # (req, future)
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0
+    remaining = len(reqs)
+    try:
+        while remaining:
+            t = now()
+            while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= t):
+                preparing.append((reqs[nxt], pool.submit(prepare, reqs[nxt], storage)))
+                nxt += 1
+            while preparing and preparing[0][1].done():
+                r, fut = preparing.popleft()
+                waiting.append((r, fut.result()))
+            while waiting:
+                r, d = waiting[0]
+                slot = batch.admit(d, r.steps)
+                if slot is None:
+                    break
+                waiting.popleft()
+                resident[slot] = (r, d)
+                outs[r.rid].admitted = now()
+            _, enq, done, _ = batch.stats()
+            if resident and enq - done < max_ahead * steps_per_tick:
+                batch.step(steps_per_tick)
+            for slot in batch.poll():
+                r, d = resident.pop(slot)
+                batch.release(slot)
+                finishing.append((r, pool.submit(finish, d, keep_fields)))
+            still = []
+            for r, fut in finishing:
+                if fut.done():
+                    st, rho, u, nupd = fut.result()
+                    o = outs[r.rid]
+                    o.done, o.status, o.rho, o.u, o.updated_cells = now(), st, rho, u, nupd
+                    remaining -= 1
+                else:
+                    still.append((r, fut))
+            finishing = still
+            if not resident or enq - done >= max_ahead * steps_per_tick:
+                time.sleep(2e-4)
+    finally:
+        pool.shutdown(wait=True)
+        batch.destroy()
+    wall = now()
+    res = [outs[r.rid] for r in reqs]
+    return res, summarise("continuous-batching", res, wall, budget_bytes)
+
+
+def serve_serial(trace, storage="fp16s", workers=4, keep_fields=False, realtime=True):
+    """Serve a trace one solve at a time (preparation of later requests still
+    overlaps on the worker pool)."""
+    pool = cf.ThreadPoolExecutor(max_workers=workers)
+    reqs = sorted(trace, key=lambda r: r.arrival)
+    outs = []
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0
+    futures = {}
+    nxt = 0
+    try:
+        for r in reqs:
+            if realtime:  # the device is idle until this request arrives
+                time.sleep(max(0.0, r.arrival - now()))
+            while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= now()):
+                futures[reqs[nxt].rid] = pool.submit(prepare, reqs[nxt], storage)
+                nxt += 1
+            d = futures.pop(r.rid).result()
+            o = Outcome(r.rid, r.arrival, steps=r.steps, admitted=now())
+            st = d.step_status(r.steps)
+            st2, o.rho, o.u, o.updated_cells = finish(d, keep_fields)
+            o.status = st if st != 0 else st2
+            o.done = now()
+            outs.append(o)
+    finally:
+        pool.shutdown(wait=True)
+    wall = now()
+    return outs, summarise("one-at-a-time", outs, wall)
+
+
+def run_packed(specs, storage="fp16s", steps=None, budget_bytes=None):
+    """Advance independent periodic/channel domains together (one packed launch
+    per step) and one after another; returns aggregate MLUPS of both."""
+    import torch
+
+    def build(s):
+        d = capi.Domain(s.flags, periodic=s.periodic, storage=storage)
+        d.set_params(s.tau, 1.0 / s.tau, 1.0)
+        d.init_fields(None, s.u)
+        return d
+
+    nsteps = [steps or s.steps for s in specs]
+    upd = sum(s.ncells * n for s, n in zip(specs, nsteps))
+    # one after another
+    doms = [build(s) for s in specs]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for d, n in zip(doms, nsteps):
+        d.step(n)
+    serial = time.perf_counter() - t
+    for d in doms:
+        d.destroy()
+    # packed
+    doms = [build(s) for s in specs]
+    if budget_bytes is None:
+        budget_bytes = sum(int(d.info().device_bytes) for d in doms) + (1 << 30)
+    b = capi.Batch(budget_bytes, storage)
+    t = time.perf_counter()
+    slots = [b.admit(d, n) for d, n in zip(doms, nsteps)]
+    assert all(s is not None for s in slots)
+    left = set(slots)
+    while left:
+        b.step(8)
+        for s in b.poll():
+            left.discard(s)
+    packed = time.perf_counter() - t
+    for s in slots:
+        b.release(s)
+    b.destroy()
+    for d in doms:
+        d.destroy()
+    return {"domains": len(specs), "cells": int(sum(s.ncells for s in specs)), "cell_updates": int(upd),
+            "serial_s": round(serial, 4), "packed_s": round(packed, 4),
+            "serial_mlups": round(upd / serial / 1e6, 1), "packed_mlups": round(upd / packed / 1e6, 1),
+            "speedup": round(serial / packed, 3)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--steps-scale", type=float, default=1.0)
+    ap.add_argument("--storage", default="fp16s")
+    ap.add_argument("--no-serial", action="store_true")
+    args = ap.parse_args(argv)
+    import torch
+
+    torch.cuda.set_device(0)
+    tr = I.serving_trace(count=args.requests, rate=args.rate,
+                         steps_lo=max(1, int(1000 * args.steps_scale)), steps_hi=max(1, int(5000 * args.steps_scale)))
+    out = {}
+    _, out["continuous"] = serve_continuous(tr, storage=args.storage)
+    print(json.dumps(out["continuous"]), file=sys.stderr, flush=True)
+    if not args.no_serial:
+        _, out["serial"] = serve_serial(tr, storage=args.storage)
+        print(json.dumps(out["serial"]), file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

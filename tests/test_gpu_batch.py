@@ -1,0 +1,177 @@
+"""Packed multi-domain execution and the serving loop on the GPU.
+
+Each domain advanced inside a packed launch must end in exactly the state it
+reaches when advanced alone (same per-cell arithmetic, same kernels), so the
+comparisons here are bitwise.  The graph-replay test checks that replaying a
+captured graph several times, with eager work in between, gives the same
+state as eager launches."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2204_10566_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2204_10566_amd import capi
+
+    return capi
+
+
+def build(capi, spec, storage):
+    d = capi.Domain(spec.flags, periodic=spec.periodic, storage=storage)
+    d.set_params(spec.tau, 1.0 / spec.tau, 1.0)
+    d.init_fields(None, spec.u.astype(np.float32))
+    return d
+
+
+def small_specs(count, seed, lo=10, hi=26):
+    specs = I.batched_domains(count=count, seed=seed, lo=lo, hi=hi, materialise=True)
+    rng = np.random.default_rng(seed)
+    for s in specs:
+        s.steps = int(rng.integers(5, 40))
+    return specs
+
+
+@pytest.mark.parametrize("storage", ["fp16s", "fp32"])
+def test_alone_equals_mix_staggered(capi, storage):
+    specs = small_specs(6, 1)
+    say(f"alone vs mix {storage}: " + ", ".join(f"{s.kind}{s.nx}x{s.ny}x{s.nz}/{s.steps}" for s in specs))
+    alone = []
+    for s in specs:
+        d = build(capi, s, storage)
+        d.step(s.steps)
+        alone.append(d.populations())
+        d.destroy()
+    doms = [build(capi, s, storage) for s in specs]
+    b = capi.Batch(1 << 34, storage)
+    slots = {}
+    order = [[0, 1, 2], [3], [4, 5]]
+    pending = set()
+    for group in order:
+        for k in group:
+            slots[k] = b.admit(doms[k], specs[k].steps)
+            pending.add(slots[k])
+        b.step(3)
+    while pending:
+        b.step(4)
+        for s in b.poll():
+            pending.discard(s)
+    for k, s in slots.items():
+        b.release(s)
+        got = doms[k].populations()
+        assert np.array_equal(got, alone[k]), f"domain {k} differs"
+        doms[k].destroy()
+    b.destroy()
+
+
+def test_budget_limits_admission(capi):
+    spec = I.DomainSpec(kind="tgv", nx=20, ny=20, nz=20, tau=0.6, steps=5).materialise()
+    doms = [build(capi, spec, "fp16s") for _ in range(3)]
+    size = int(doms[0].info().device_bytes)
+    say(f"budget admission, {size} bytes per domain")
+    b = capi.Batch(2 * size, "fp16s")
+    s0 = b.admit(doms[0], 5)
+    s1 = b.admit(doms[1], 5)
+    assert s0 is not None and s1 is not None
+    assert b.admit(doms[2], 5) is None  # over budget: the caller queues it
+    b.step(5)
+    assert sorted(b.poll(wait=True)) == sorted([s0, s1])
+    b.release(s0)
+    s2 = b.admit(doms[2], 5)
+    assert s2 is not None
+    b.release(s1)
+    b.step(5)
+    assert b.poll(wait=True) == [s2]
+    b.release(s2)
+    # all three took the same 5 steps from the same start
+    p = [d.populations() for d in doms]
+    assert np.array_equal(p[0], p[1]) and np.array_equal(p[0], p[2])
+    for d in doms:
+        d.destroy()
+    b.destroy()
+
+
+def test_release_churn_and_compaction(capi):
+    """Admit and release many domains so that the packed table is compacted
+    while a long-running domain stays resident; every result still equals
+    its stand-alone run."""
+    long_spec = I.DomainSpec(kind="tgv", nx=40, ny=40, nz=40, tau=0.62, steps=60).materialise()
+    shorts = small_specs(10, 3, lo=30, hi=44)  # ~400-1300 tiles each
+    say("churn: one long domain, ten short ones")
+    ref = {}
+    for k, s in enumerate([long_spec] + shorts):
+        d = build(capi, s, "fp16s")
+        d.step(s.steps)
+        ref[k] = d.populations()
+        d.destroy()
+    b = capi.Batch(1 << 34, "fp16s")
+    long_d = build(capi, long_spec, "fp16s")
+    long_slot = b.admit(long_d, long_spec.steps)
+    active = {}
+    queue = list(enumerate(shorts, start=1))
+    finished = {}
+    while queue or active or long_slot is not None:
+        while queue and len(active) < 3:
+            k, s = queue.pop(0)
+            d = build(capi, s, "fp16s")
+            active[b.admit(d, s.steps)] = (k, d)
+        b.step(2)
+        for slot in b.poll():
+            if slot == long_slot:
+                b.release(slot)
+                finished[0] = long_d.populations()
+                long_d.destroy()
+                long_slot = None
+            else:
+                k, d = active.pop(slot)
+                b.release(slot)
+                finished[k] = d.populations()
+                d.destroy()
+    b.destroy()
+    for k in ref:
+        assert np.array_equal(finished[k], ref[k]), f"domain {k} differs"
+
+
+def test_serving_alone_equals_mix(capi):
+    from paper_2204_10566_amd import serve
+
+    tr = I.serving_trace(count=6, rate=200.0, seed=5, steps_lo=20, steps_hi=80)
+    for r in tr:  # shrink the grids for the test
+        n = 32 if r.rid % 2 else 40
+        r.nozzle = I.Nozzle(n=n, length=4 * n, R=n / 4.0, r_throat=n / 4.0 * 0.4, inlet_len=n / 2.0,
+                            throat_len=n)
+    say("serving: 6 small requests, continuous vs one-at-a-time")
+    mix, s_mix = serve.serve_continuous(tr, storage="fp16s", budget_bytes=1 << 32, steps_per_tick=4,
+                                        keep_fields=True, realtime=False)
+    alone, s_alone = serve.serve_serial(tr, storage="fp16s", keep_fields=True, realtime=False)
+    say(f"  {s_mix}\n  {s_alone}")
+    by = {o.rid: o for o in alone}
+    for o in mix:
+        a = by[o.rid]
+        assert o.status == a.status
+        assert np.array_equal(o.rho, a.rho) and np.array_equal(o.u, a.u), f"request {o.rid} differs"
+
+
+def test_graph_replays_match_eager_steps(capi):
+    """lbm_step(16) replays a captured 16-step graph; three replays with host
+    reads in between equal 48 single eager steps."""
+    spec = I.DomainSpec(kind="channel", nx=36, ny=18, nz=12, tau=0.57, steps=48).materialise()
+    say("graph replays vs eager steps")
+    g = build(capi, spec, "fp32")
+    for _ in range(3):
+        g.step(16)
+        g.moments()
+    e = build(capi, spec, "fp32")
+    for _ in range(48):
+        e.step(1)
+    assert np.array_equal(g.populations(), e.populations())
