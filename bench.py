@@ -75,18 +75,53 @@ def copy_ceiling(torch, stream, nbytes, reps=20):
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     with torch.cuda.stream(stream):
+        # an elementwise kernel reading n floats and writing n floats
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(reps):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
     del src, dst
     return {"gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1), "bytes_per_copy": 2 * n * 4, "us_per_copy": round(ms * 1e3, 2)}
+
+
+def batched_leg(storage="fp16s"):
+    """64 independent periodic / channel domains (edges 16..128, cubes and
+    2:1:1 boxes, tau in [0.51, 0.8]), 500 steps each: one packed launch per
+    step versus one domain after another."""
+    from paper_2204_10566_amd import inputs as I
+    from paper_2204_10566_amd import serve
+
+    specs = I.batched_domains(count=64, seed=0, steps=500, materialise=True)
+    out = serve.run_packed(specs, storage=storage)
+    out["storage"] = storage
+    return out
+
+
+def serving_leg(full: bool, storage="fp16s"):
+    """Poisson arrivals (20 requests/s) of nozzle-like solves (64..128 cross
+    section, length 4n..8n, throat/pipe ratio 0.25..0.5, Re 500..6500),
+    continuous batching versus one at a time on the same trace."""
+    from paper_2204_10566_amd import inputs as I
+    from paper_2204_10566_amd import serve
+
+    if full:
+        tr = I.serving_trace(count=200, rate=20.0, seed=0)
+        label = "200 requests, 1000-5000 steps each"
+    else:
+        tr = I.serving_trace(count=60, rate=20.0, seed=0, steps_lo=250, steps_hi=1250)
+        label = "first 60 requests of the trace with step counts scaled by 1/4 (250-1250)"
+    _, cont = serve.serve_continuous(tr, storage=storage)
+    log(f"serving continuous: {cont}")
+    _, ser = serve.serve_serial(tr, storage=storage)
+    log(f"serving serial: {ser}")
+    return {"trace": label, "storage": storage, "continuous": cont, "serial": ser,
+            "p99_ratio_serial_over_continuous": round(ser["p99_s"] / cont["p99_s"], 3)}
 
 
 def cpu_baseline(cfg, nsteps=3):
@@ -122,6 +157,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16s", "bf16s"])
+    ap.add_argument("--serving", default="reduced", choices=["off", "reduced", "full"])
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path: "
@@ -204,6 +241,13 @@ def main():
                        "steps": vsteps, "status": int(vrc)}
             log(f"{st}: {v:.0f} fluid MLUPS ({v / mlups:.2f}x fp32)")
         out["variants"] = var
+    if not args.no_batched:
+        log("batched: 64 domains, packed vs serial")
+        out["batched"] = batched_leg()
+        log(f"batched: {out['batched']}")
+    if args.serving != "off":
+        log(f"serving ({args.serving} trace)")
+        out["serving"] = serving_leg(args.serving == "full")
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg)

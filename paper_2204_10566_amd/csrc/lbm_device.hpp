@@ -412,8 +412,9 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const Tile
 }
 
 // Packed multi-domain step.  ctrl[0] = number of tile records, ctrl[1] =
-// global step.  A persistent grid walks the table; each wave takes whole
-// tiles, each tile belongs to one domain.
+// global step.  One wave per tile record (the host keeps the grid at least
+// as large as the table); each tile belongs to one domain, whose descriptor
+// says whether it takes part in this step.
 template <int ST, bool HIGH1>
 __global__ __launch_bounds__(kBlock) void k_stream_collide_batched(const KDomain *__restrict__ doms,
                                                                 const BatchTileRec *__restrict__ tiles,
