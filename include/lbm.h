@@ -239,9 +239,12 @@ int lbm_batch_step(lbm_batch *b, int n);
 
 /*
  * Report domains whose admitted steps have all completed on the device
- * since the last poll.  Non-blocking unless wait != 0 (then waits for all
- * enqueued work).  done_slots receives up to max slot ids; *n_done their
- * count.  A completed domain stays resident until lbm_batch_release.
+ * since the last poll, and domains that went unstable (rho <= 0 or a
+ * non-finite value): those are evicted, take no further steps, and are
+ * reported once the steps already enqueued for them have completed.
+ * Non-blocking unless wait != 0 (then waits for all enqueued work first).
+ * done_slots receives up to max slot ids; *n_done their count.  A reported
+ * domain stays resident until lbm_batch_release.
  */
 int lbm_batch_poll(lbm_batch *b, int wait, int *done_slots, int max, int *n_done);
 

@@ -230,6 +230,58 @@ struct lbm_domain {
 
 namespace {
 
+// Device memory of domains comes from the stream-ordered allocator: a free
+// does not synchronise the device (a service frees domains while other
+// domains keep running), and freed memory stays in the device's pool for
+// the next domain.
+std::mutex g_pool_mutex;
+bool g_pool_ready[64];
+
+void pool_setup(int device)
+{
+    std::lock_guard<std::mutex> lock(g_pool_mutex);
+    if (device < 0 || device >= 64 || g_pool_ready[device])
+        return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    g_pool_ready[device] = true;
+}
+
+hipError_t dalloc(hipStream_t s, void **p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0)
+        return hipSuccess;
+    hipError_t e = hipMallocAsync(p, n, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+    }
+    return e;
+}
+
+void dfree(hipStream_t s, void *p)
+{
+    if (p)
+        (void)hipFreeAsync(p, s);
+}
+
+// Copies between host memory and the domain's memory, in the domain's
+// stream order; they return once the copy is complete.
+hipError_t copy_sync(hipStream_t s, void *dst, const void *src, size_t n, hipMemcpyKind kind)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipError_t e = hipMemcpyAsync(dst, src, n, kind, s);
+    if (e != hipSuccess)
+        return e;
+    return hipStreamSynchronize(s);
+}
+
 KDomain kdomain(const lbm_domain *d)
 {
     KDomain k{};
@@ -317,7 +369,7 @@ int sync_status(lbm_domain *d)
 {
     HIP_TRY(hipStreamSynchronize(d->stream));
     uint32_t st = 0;
-    HIP_TRY(hipMemcpy(&st, d->d_status, sizeof st, hipMemcpyDeviceToHost));
+    HIP_TRY(copy_sync(d->stream, &st, d->d_status, sizeof st, hipMemcpyDeviceToHost));
     if (st)
         d->unstable = true;
     return LBM_OK;
@@ -344,19 +396,22 @@ void release_graph(lbm_domain *d)
 void free_domain(lbm_domain *d)
 {
     release_graph(d);
-    if (d->own_buffers) {
-        (void)hipFree(d->buf[0]);
-        (void)hipFree(d->buf[1]);
+    if (d->stream) {
+        hipStream_t s = d->stream;
+        if (d->own_buffers) {
+            dfree(s, d->buf[0]);
+            dfree(s, d->buf[1]);
+        }
+        dfree(s, d->d_flags);
+        dfree(s, d->d_tiles);
+        dfree(s, d->d_wall);
+        dfree(s, d->d_inlet);
+        dfree(s, d->d_inlrec);
+        dfree(s, d->d_uin);
+        dfree(s, d->d_status);
+        if (d->own_stream)
+            (void)hipStreamDestroy(s);
     }
-    (void)hipFree(d->d_flags);
-    (void)hipFree(d->d_tiles);
-    (void)hipFree(d->d_wall);
-    (void)hipFree(d->d_inlet);
-    (void)hipFree(d->d_inlrec);
-    (void)hipFree(d->d_uin);
-    (void)hipFree(d->d_status);
-    if (d->own_stream && d->stream)
-        (void)hipStreamDestroy(d->stream);
     delete d;
 }
 
@@ -440,15 +495,10 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
             return bail(fail(LBM_ERR_DEVICE, "hipStreamCreate failed"));
         d->own_stream = true;
     }
+    pool_setup(d->device);
     auto dmalloc = [&](void **p, size_t n) -> bool {
-        if (n == 0) {
-            *p = nullptr;
-            return true;
-        }
-        if (hipMalloc(p, n) != hipSuccess) {
-            (void)hipGetLastError();
+        if (dalloc(d->stream, p, n) != hipSuccess)
             return false;
-        }
         d->device_bytes += n;
         return true;
     };
@@ -466,7 +516,9 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
         !dmalloc((void **)&d->d_wall, T.wall.size() * 4) || !dmalloc((void **)&d->d_inlet, T.inlet.size() * 4) ||
         !dmalloc((void **)&d->d_inlrec, T.inlrec.size() * 4) || !dmalloc((void **)&d->d_status, sizeof(uint32_t)))
         return bail(fail(LBM_ERR_OOM, "domain tables"));
-    auto up = [](void *dst, const void *src, size_t n) { return n == 0 || hipMemcpy(dst, src, n, hipMemcpyHostToDevice) == hipSuccess; };
+    auto up = [&](void *dst, const void *src, size_t n) {
+        return copy_sync(d->stream, dst, src, n, hipMemcpyHostToDevice) == hipSuccess;
+    };
     if (!up(d->d_flags, flags, ncells) || !up(d->d_tiles, T.recs.data(), T.recs.size() * sizeof(TileRec)) ||
         !up(d->d_wall, T.wall.data(), T.wall.size() * 4) || !up(d->d_inlet, T.inlet.data(), T.inlet.size() * 4) ||
         !up(d->d_inlrec, T.inlrec.data(), T.inlrec.size() * 4))
@@ -483,20 +535,58 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     return LBM_OK;
 }
 
-int capture_graph(lbm_domain *d)
+// Append a kernel node after `prev` (or as a root when prev is null).  The
+// argument values are copied into the node.
+hipError_t add_kernel_node(hipGraph_t g, hipGraphNode_t prev, const void *func, uint32_t grid, uint32_t block,
+                           void **args, hipGraphNode_t *out)
+{
+    hipKernelNodeParams p{};
+    p.func = const_cast<void *>(func);
+    p.gridDim = dim3(grid);
+    p.blockDim = dim3(block);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    return hipGraphAddKernelNode(out, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+}
+
+template <int ST, bool H> const void *step_kernel_t() { return (const void *)k_stream_collide<ST, H>; }
+
+const void *step_kernel(int storage, bool h1)
+{
+    switch (storage) {
+    case LBM_FP32:
+        return h1 ? step_kernel_t<ST_FP32, true>() : step_kernel_t<ST_FP32, false>();
+    case LBM_FP16S:
+        return h1 ? step_kernel_t<ST_FP16S, true>() : step_kernel_t<ST_FP16S, false>();
+    default:
+        return h1 ? step_kernel_t<ST_BF16S, true>() : step_kernel_t<ST_BF16S, false>();
+    }
+}
+
+// Build (not capture) a graph of kGraphSteps chained stream-collide nodes
+// starting from buffer 0; built node by node so that work other threads
+// issue meanwhile cannot interfere.
+int build_graph(lbm_domain *d)
 {
     release_graph(d);
-    hipStream_t s = d->stream;
-    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k)
-        e = launch_step(d, (uint32_t)(k & 1));
     hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(s, &g);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (g)
+    HIP_TRY(hipGraphCreate(&g, 0));
+    KDomain k = kdomain(d);
+    const TileRec *tiles = d->d_tiles;
+    uint32_t nt = (uint32_t)d->ntiles;
+    const void *fn = step_kernel(d->storage, d->omega_h == 1.0);
+    hipGraphNode_t prev = nullptr;
+    for (int s = 0; s < kGraphSteps; ++s) {
+        uint32_t src = (uint32_t)(s & 1);
+        void *args[] = {&k, &tiles, &nt, &src};
+        hipGraphNode_t node = nullptr;
+        hipError_t e = add_kernel_node(g, prev, fn, step_grid(d), kBlock, args, &node);
+        if (e != hipSuccess) {
             (void)hipGraphDestroy(g);
-        return fail(LBM_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+            return fail(LBM_ERR_DEVICE, "graph node: %s", hipGetErrorString(e));
+        }
+        prev = node;
     }
     d->graph_def = g;
     HIP_TRY(hipGraphInstantiate(&d->graph, g, nullptr, nullptr, 0));
@@ -577,15 +667,12 @@ int lbm_set_inlet_cells(lbm_domain *d, const float *u_inlet)
     if (n == 0)
         return LBM_OK;
     if (!d->d_uin) {
-        if (hipMalloc((void **)&d->d_uin, 3 * n * sizeof(float)) != hipSuccess) {
-            (void)hipGetLastError();
-            d->d_uin = nullptr;
+        if (dalloc(d->stream, (void **)&d->d_uin, 3 * n * sizeof(float)) != hipSuccess)
             return fail(LBM_ERR_OOM, "inlet velocity buffer");
-        }
         d->device_bytes += 3 * n * sizeof(float);
         d->graph_dirty = true;
     }
-    HIP_TRY(hipMemcpy(d->d_uin, u_inlet, 3 * n * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(copy_sync(d->stream, d->d_uin, u_inlet, 3 * n * sizeof(float), hipMemcpyHostToDevice));
     return LBM_OK;
 }
 
@@ -611,20 +698,22 @@ int lbm_init_fields(lbm_domain *d, const float *rho, const float *u)
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     float *dr = nullptr, *du = nullptr;
     int rc = LBM_OK;
-    if (rho && hipMalloc((void **)&dr, d->ncells * sizeof(float)) != hipSuccess)
+    if (rho && dalloc(d->stream, (void **)&dr, d->ncells * sizeof(float)) != hipSuccess)
         rc = fail(LBM_ERR_OOM, "staging buffer");
-    if (rc == LBM_OK && u && hipMalloc((void **)&du, 3 * d->ncells * sizeof(float)) != hipSuccess)
+    if (rc == LBM_OK && u && dalloc(d->stream, (void **)&du, 3 * d->ncells * sizeof(float)) != hipSuccess)
         rc = fail(LBM_ERR_OOM, "staging buffer");
-    if (rc == LBM_OK && rho && hipMemcpy(dr, rho, d->ncells * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    if (rc == LBM_OK && rho &&
+        copy_sync(d->stream, dr, rho, d->ncells * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         rc = fail(LBM_ERR_DEVICE, "upload of rho failed");
-    if (rc == LBM_OK && u && hipMemcpy(du, u, 3 * d->ncells * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    if (rc == LBM_OK && u &&
+        copy_sync(d->stream, du, u, 3 * d->ncells * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         rc = fail(LBM_ERR_DEVICE, "upload of u failed");
     if (rc == LBM_OK)
         rc = init_eq(d, dr, du);
     if (rc == LBM_OK && hipStreamSynchronize(d->stream) != hipSuccess)
         rc = fail(LBM_ERR_DEVICE, "initialisation failed");
-    (void)hipFree(dr);
-    (void)hipFree(du);
+    dfree(d->stream, dr);
+    dfree(d->stream, du);
     return rc;
 }
 
@@ -648,7 +737,7 @@ int lbm_step(lbm_domain *d, int n)
     }
     if (left >= kGraphSteps) {
         if (d->graph_dirty)
-            if (int rc = capture_graph(d))
+            if (int rc = build_graph(d))
                 return rc;
         while (left >= kGraphSteps) {
             HIP_TRY(hipGraphLaunch(d->graph, d->stream));
@@ -693,14 +782,14 @@ int lbm_get_moments(lbm_domain *d, float *rho, float *u)
     if (!rho || !u)
         return fail(LBM_ERR_ARG, "null output");
     float *dr = nullptr;
-    if (hipMalloc((void **)&dr, 4 * d->ncells * sizeof(float)) != hipSuccess)
+    if (dalloc(d->stream, (void **)&dr, 4 * d->ncells * sizeof(float)) != hipSuccess)
         return fail(LBM_ERR_OOM, "staging buffer");
     int rc = lbm_get_moments_device(d, dr, dr + d->ncells);
-    if (rc == LBM_OK && (hipMemcpy(rho, dr, d->ncells * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
-                         hipMemcpy(u, dr + d->ncells, 3 * d->ncells * sizeof(float), hipMemcpyDeviceToHost) !=
-                             hipSuccess))
+    if (rc == LBM_OK &&
+        (copy_sync(d->stream, rho, dr, d->ncells * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+         copy_sync(d->stream, u, dr + d->ncells, 3 * d->ncells * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess))
         rc = fail(LBM_ERR_DEVICE, "download failed");
-    (void)hipFree(dr);
+    dfree(d->stream, dr);
     return rc;
 }
 
@@ -713,7 +802,7 @@ int lbm_get_populations(lbm_domain *d, float *f)
     if (d->batch)
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     float *df = nullptr;
-    if (hipMalloc((void **)&df, (size_t)Q * d->ncells * sizeof(float)) != hipSuccess)
+    if (dalloc(d->stream, (void **)&df, (size_t)Q * d->ncells * sizeof(float)) != hipSuccess)
         return fail(LBM_ERR_OOM, "staging buffer");
     const KDomain k = kdomain(d);
     const uint32_t blocks = (uint32_t)((d->ncells + 255) / 256);
@@ -722,10 +811,10 @@ int lbm_get_populations(lbm_domain *d, float *f)
                            (uint32_t)d->cur, df);
     });
     int rc = LBM_OK;
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(d->stream) != hipSuccess ||
-        hipMemcpy(f, df, (size_t)Q * d->ncells * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipGetLastError() != hipSuccess ||
+        copy_sync(d->stream, f, df, (size_t)Q * d->ncells * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
         rc = fail(LBM_ERR_DEVICE, "population export failed");
-    (void)hipFree(df);
+    dfree(d->stream, df);
     return rc;
 }
 
@@ -738,10 +827,10 @@ int lbm_set_populations(lbm_domain *d, const float *f)
     if (d->batch)
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     float *df = nullptr;
-    if (hipMalloc((void **)&df, (size_t)Q * d->ncells * sizeof(float)) != hipSuccess)
+    if (dalloc(d->stream, (void **)&df, (size_t)Q * d->ncells * sizeof(float)) != hipSuccess)
         return fail(LBM_ERR_OOM, "staging buffer");
     int rc = LBM_OK;
-    if (hipMemcpy(df, f, (size_t)Q * d->ncells * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+    if (copy_sync(d->stream, df, f, (size_t)Q * d->ncells * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
         rc = fail(LBM_ERR_DEVICE, "upload failed");
     if (rc == LBM_OK) {
         const KDomain k = kdomain(d);
@@ -753,7 +842,7 @@ int lbm_set_populations(lbm_domain *d, const float *f)
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(d->stream) != hipSuccess)
             rc = fail(LBM_ERR_DEVICE, "population import failed");
     }
-    (void)hipFree(df);
+    dfree(d->stream, df);
     return rc;
 }
 

@@ -46,24 +46,39 @@ class Outcome:
         return self.done - self.arrival
 
 
+_timing_lock = __import__("threading").Lock()
+_timing = collections.Counter()
+
+
+def _account(key, t0):
+    with _timing_lock:
+        _timing[key] += time.perf_counter() - t0
+
+
 def prepare(req: I.Request, storage: str, stream=None) -> capi.Domain:
+    t0 = time.perf_counter()
     b = req.build()
+    _account("build_inputs_s", t0)
+    t1 = time.perf_counter()
     d = capi.Domain(b["flags"], periodic=0, storage=storage, stream=stream)
     d.set_params(b["tau"], 1.0 / b["tau"], 1.0)
     d.set_inlet_cells(b["uin_cells"])
     d.init_fields()
+    _account("create_domain_s", t1)
     return d
 
 
 def finish(d: capi.Domain, keep_fields: bool):
     """Copy the result to the host and free the domain.  Returns (status, rho,
     u, updated cells); status is LBM_ERR_UNSTABLE if any step went unstable."""
+    t0 = time.perf_counter()
     status = d.step_status(0)
     rho, u = d.moments()
     info = d.info()
     d.destroy()
     if not keep_fields:
         rho, u = None, None
+    _account("finish_s", t0)
     return status, rho, u, int(info.n_updated)
 
 
@@ -76,7 +91,11 @@ def summarise(mode, outs, wall, budget=None):
     lat = [o.latency for o in outs]
     p50, p99 = percentiles(lat)
     upd = sum(o.updated_cells * o.steps for o in outs if o.status == 0)
+    with _timing_lock:
+        host = {k: round(v, 3) for k, v in _timing.items()}
+        _timing.clear()
     return {
+        "host_time_s": host,
         "mode": mode,
         "requests": len(outs),
         "unstable": sum(1 for o in outs if o.status != 0),
@@ -90,8 +109,14 @@ def summarise(mode, outs, wall, budget=None):
 
 
 def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8, max_ahead=2, workers=4,
-                     keep_fields=False, realtime=True):
-    """Serve a trace with continuous batching.  Returns (outcomes, summary)."""
+                     keep_fields=False, realtime=True, work_cap_cells=None, order="fifo"):
+    """Serve a trace with continuous batching.  Returns (outcomes, summary).
+
+    Admission is limited by the HBM budget and, if work_cap_cells is set,
+    by the number of updated cells resident at once (enough to saturate the
+    device; more only slows every resident solve).  order: "fifo" admits in
+    arrival order, "sjf" admits the waiting request with the least work
+    (updated cells x steps) first."""
     import torch
 
     if budget_bytes is None:
@@ -104,7 +129,9 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
     nxt = 0
     preparing = collections.deque()  # (req, future) in arrival order
     waiting = collections.deque()    # (req, domain) prepared, not yet admitted
-    resident = {}                    # slot -> (req, domain)
+    resident = {}                    # slot -> (req, domain, updated cells)
+    resident_cells = 0
+    idle_ticks = 0                   # loop turns with nothing resident
     finishing = []                   # (req, future)
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0
@@ -117,20 +144,29 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
                 nxt += 1
             while preparing and preparing[0][1].done():
                 r, fut = preparing.popleft()
-                waiting.append((r, fut.result()))
+                d = fut.result()
+                waiting.append((r, d, int(d.info().n_updated)))
+            if order == "sjf" and len(waiting) > 1:
+                waiting = collections.deque(sorted(waiting, key=lambda e: e[2] * e[0].steps))
             while waiting:
-                r, d = waiting[0]
+                r, d, nupd = waiting[0]
+                if work_cap_cells and resident and resident_cells + nupd > work_cap_cells:
+                    break
                 slot = batch.admit(d, r.steps)
                 if slot is None:
                     break
                 waiting.popleft()
-                resident[slot] = (r, d)
+                resident[slot] = (r, d, nupd)
+                resident_cells += nupd
                 outs[r.rid].admitted = now()
             _, enq, done, _ = batch.stats()
             if resident and enq - done < max_ahead * steps_per_tick:
                 batch.step(steps_per_tick)
+            elif not resident:
+                idle_ticks += 1
             for slot in batch.poll():
-                r, d = resident.pop(slot)
+                r, d, nupd = resident.pop(slot)
+                resident_cells -= nupd
                 batch.release(slot)
                 finishing.append((r, pool.submit(finish, d, keep_fields)))
             still = []
@@ -150,7 +186,11 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
         batch.destroy()
     wall = now()
     res = [outs[r.rid] for r in reqs]
-    return res, summarise("continuous-batching", res, wall, budget_bytes)
+    s = summarise("continuous-batching", res, wall, budget_bytes)
+    s["work_cap_cells"] = work_cap_cells
+    s["order"] = order
+    s["idle_loop_turns"] = idle_ticks
+    return res, s
 
 
 def serve_serial(trace, storage="fp16s", workers=4, keep_fields=False, realtime=True):
@@ -236,6 +276,9 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--steps-scale", type=float, default=1.0)
     ap.add_argument("--storage", default="fp16s")
+    ap.add_argument("--policies", default="fifo",
+                    help="comma-separated continuous-batching policies: fifo, sjf, fifo@CELLS, sjf@CELLS "
+                         "(CELLS caps resident updated cells, e.g. fifo@8e6)")
     ap.add_argument("--no-serial", action="store_true")
     args = ap.parse_args(argv)
     import torch
@@ -244,8 +287,11 @@ def main(argv=None):
     tr = I.serving_trace(count=args.requests, rate=args.rate,
                          steps_lo=max(1, int(1000 * args.steps_scale)), steps_hi=max(1, int(5000 * args.steps_scale)))
     out = {}
-    _, out["continuous"] = serve_continuous(tr, storage=args.storage)
-    print(json.dumps(out["continuous"]), file=sys.stderr, flush=True)
+    for pol in args.policies.split(","):
+        order, _, cap = pol.partition("@")
+        _, s = serve_continuous(tr, storage=args.storage, order=order, work_cap_cells=int(float(cap)) if cap else None)
+        out[f"continuous_{pol}"] = s
+        print(json.dumps(s), file=sys.stderr, flush=True)
     if not args.no_serial:
         _, out["serial"] = serve_serial(tr, storage=args.storage)
         print(json.dumps(out["serial"]), file=sys.stderr, flush=True)

@@ -162,6 +162,45 @@ def test_serving_alone_equals_mix(capi):
         assert np.array_equal(o.rho, a.rho) and np.array_equal(o.u, a.u), f"request {o.rid} differs"
 
 
+def test_unstable_domain_is_evicted(capi):
+    """A domain that goes unstable inside a batch is reported long before
+    its step count, released as unstable, and the other domains finish with
+    their stand-alone results.  The instability is forced from the host: the
+    domain starts from a negative-density state."""
+    specs = small_specs(3, 4)
+    for s in specs:
+        s.steps = 200
+    ref = {}
+    for k in (0, 2):
+        d = build(capi, specs[k], "fp16s")
+        d.step(specs[k].steps)
+        ref[k] = d.populations()
+        d.destroy()
+    doms = [build(capi, s, "fp16s") for s in specs]
+    bad = doms[1]
+    bad.set_populations(-0.01 * np.ones((27,) + specs[1].flags.shape, np.float32))
+    say("eviction of an unstable domain")
+    b = capi.Batch(1 << 34, "fp16s")
+    slots = [b.admit(d, s.steps) for d, s in zip(doms, specs)]
+    reported = {}
+    ticks = 0
+    while len(reported) < 3:
+        b.step(2)
+        ticks += 1
+        for s in b.poll():
+            reported[s] = ticks
+    assert reported[slots[1]] < 40  # evicted early, not after 200 steps
+    for k, s in enumerate(slots):
+        b.release(s)
+    assert doms[1].step_status(0) == capi.ERR_UNSTABLE
+    for k in (0, 2):
+        assert doms[k].step_status(0) == capi.OK
+        assert np.array_equal(doms[k].populations(), ref[k])
+    for d in doms:
+        d.destroy()
+    b.destroy()
+
+
 def test_graph_replays_match_eager_steps(capi):
     """lbm_step(16) replays a captured 16-step graph; three replays with host
     reads in between equal 48 single eager steps."""
