@@ -33,16 +33,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def read_traffic(kernel: str, storage: str):
+def kernel_source_hash() -> str:
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_2204_10566_amd", "csrc", "lbm_device.hpp")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(kernel: str, storage: str, workload: str):
     """HBM traffic per launch measured with rocprofv3 counters, from the
-    committed summary (None when absent)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{storage}.txt")
+    committed summary; None when absent or when the kernel source has
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{storage}_{workload}.txt")
     if not os.path.exists(path):
         return None
+    fields = {}
     for line in open(path):
-        if line.startswith("traffic_bytes_per_launch:"):
-            return float(line.split(":", 1)[1])
-    return None
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return float(fields["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in fields else None
 
 
 def time_steps(capi, torch, cfg, storage, steps, warmup, stream):
@@ -188,7 +200,8 @@ def main():
     achieved = n_upd * bpc / (ms_step * 1e-3) / 1e9
     log(f"{args.storage}: {ms_step * 1e3:.2f} us/step, {mlups:.0f} fluid MLUPS, {achieved:.0f} GB/s algorithmic, "
         f"status {rc}")
-    traffic = read_traffic("stream_collide", args.storage)
+    traffic_bytes = read_traffic("stream_collide", args.storage, "nozzle96x96x768")
+    traffic = None if traffic_bytes is None else round(traffic_bytes / (ms_step * 1e-3) / 1e9, 2)
     copy = copy_ceiling(torch, stream, n_upd * bpc)
     log(f"plain copy of {copy['bytes_per_copy'] / 1e6:.0f} MB: {copy['gbs']:.0f} GB/s")
 
@@ -225,6 +238,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
+            "traffic_bytes_per_launch": traffic_bytes,
+            "algorithmic_bytes_per_launch": n_upd * bpc,
             "bytes_per_fluid_cell": bpc,
             "copy_ceiling_gbs": copy["gbs"],
             "frac_of_copy": round(achieved / copy["gbs"], 4),
