@@ -111,11 +111,12 @@ void classify_cell(const uint8_t *flags, int nx, int ny, int nz, unsigned per, u
 // inlet: per cell of each wall tile the index of its inlet record (kNoRec
 // if it has no inlet link); inlrec: per record the inlet link mask and 27
 // inlet ordinals (the rank of the link's inlet cell among all inlet cells,
-// kNoRec for other links).
+// kNoRec for other links); n_inl: tiles with an inlet-term block.
 struct Tiles {
     std::vector<TileRec> recs;
     std::vector<uint32_t> wall, inlet, inlrec;
     uint64_t n_updated = 0;
+    uint32_t n_inl = 0;
 };
 
 // Build the tile list in tile order.  Work is split over host threads by
@@ -137,6 +138,7 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
         uint64_t src[Q];
         for (uint64_t t = t0; t < t1; ++t) {
             bool any = false, plain = true;
+            TileRec r{0u, (uint32_t)t, -1, 0u, kNoRec, 0u, {0u, 0u}};
             for (int l = 0; l < 64; ++l) {
                 const uint64_t c = t * 64 + l;
                 rec[l] = kNoRec;
@@ -160,19 +162,23 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
                 if (!(wl[l] & kMaskSkip)) {
                     any = true;
                     T.n_updated++;
+                    r.act[l >> 5] |= 1u << (l & 31);
+                    r.bb |= wl[l] & kMaskBB;
+                    r.inlm |= il[l];
                 }
                 if (wl[l])
                     plain = false;
             }
             if (!any)
                 continue;
-            if (plain) {
-                T.recs.push_back({(uint32_t)t, -1});
-            } else {
-                T.recs.push_back({(uint32_t)t, (int32_t)(T.wall.size() / 64)});
+            if (!plain) {
+                r.wall = (int32_t)(T.wall.size() / 64);
+                if (r.inlm)
+                    r.inl = T.n_inl++;
                 T.wall.insert(T.wall.end(), wl, wl + 64);
                 T.inlet.insert(T.inlet.end(), rec, rec + 64);
             }
+            T.recs.push_back(r);
         }
     };
     std::vector<std::thread> th;
@@ -185,10 +191,13 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
         const int32_t off = (int32_t)(out.wall.size() / 64);
         const uint32_t roff = (uint32_t)(out.inlrec.size() / kRecWords);
         for (TileRec r : part[p].recs) {
-            if (r.mask >= 0)
-                r.mask += off;
+            if (r.wall >= 0)
+                r.wall += off;
+            if (r.inl != kNoRec)
+                r.inl += out.n_inl;
             out.recs.push_back(r);
         }
+        out.n_inl += part[p].n_inl;
         out.wall.insert(out.wall.end(), part[p].wall.begin(), part[p].wall.end());
         for (uint32_t r : part[p].inlet)
             out.inlet.push_back(r == kNoRec ? kNoRec : r + roff);
@@ -215,6 +224,8 @@ struct lbm_domain {
     TileRec *d_tiles = nullptr;
     uint32_t *d_wall = nullptr, *d_inlet = nullptr, *d_inlrec = nullptr;
     float *d_uin = nullptr;                // [3][n_inlet]
+    float *d_iterm = nullptr;              // inlet terms, [27][64] per inlet tile
+    uint32_t n_inl = 0;                    // inlet tiles
     std::vector<uint64_t> inlet_cells;     // inlet cells, ascending (index = inlet ordinal)
     uint32_t *d_status = nullptr;
     uint64_t ntiles = 0, nwall = 0, n_updated = 0;
@@ -288,10 +299,7 @@ KDomain kdomain(const lbm_domain *d)
     k.buf[0] = d->buf[0];
     k.buf[1] = d->buf[1];
     k.wall = d->d_wall;
-    k.inlet = d->d_inlet;
-    k.inlrec = d->d_inlrec;
-    k.uin = d->d_uin;
-    k.n_inlet = (uint32_t)d->inlet_cells.size();
+    k.iterm = d->d_iterm;
     k.status = d->d_status;
     k.P = (uint32_t)d->P;
     k.tbytes = (uint32_t)(Q * 64 * storage_bytes(d->storage));
@@ -408,11 +416,25 @@ void free_domain(lbm_domain *d)
         dfree(s, d->d_inlet);
         dfree(s, d->d_inlrec);
         dfree(s, d->d_uin);
+        dfree(s, d->d_iterm);
         dfree(s, d->d_status);
         if (d->own_stream)
             (void)hipStreamDestroy(s);
     }
     delete d;
+}
+
+// Rebuild the inlet terms of the inlet tiles from the inlet velocity (all
+// zero while none is set).
+hipError_t build_inlet_terms(const lbm_domain *d)
+{
+    if (d->n_inl == 0)
+        return hipSuccess;
+    const uint32_t blocks = (uint32_t)((d->ntiles + 3) / 4);
+    hipLaunchKernelGGL(k_inlet_terms, dim3(blocks), dim3(256), 0, d->stream, (const TileRec *)d->d_tiles,
+                       (uint32_t)d->ntiles, (const uint32_t *)d->d_inlet, (const uint32_t *)d->d_inlrec,
+                       (const float *)d->d_uin, (uint32_t)d->inlet_cells.size(), d->d_iterm);
+    return hipGetLastError();
 }
 
 // Both buffers receive the initial state, so that cells no step updates
@@ -481,6 +503,7 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     d->nwall = T.wall.size() / 64;
     d->n_updated = T.n_updated;
     d->h_tiles = T.recs;
+    d->n_inl = T.n_inl;
     d->inlet_cells = std::move(inlet_cells);
     auto bail = [&](int code) {
         free_domain(d);
@@ -514,7 +537,8 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     }
     if (!dmalloc((void **)&d->d_flags, ncells) || !dmalloc((void **)&d->d_tiles, T.recs.size() * sizeof(TileRec)) ||
         !dmalloc((void **)&d->d_wall, T.wall.size() * 4) || !dmalloc((void **)&d->d_inlet, T.inlet.size() * 4) ||
-        !dmalloc((void **)&d->d_inlrec, T.inlrec.size() * 4) || !dmalloc((void **)&d->d_status, sizeof(uint32_t)))
+        !dmalloc((void **)&d->d_inlrec, T.inlrec.size() * 4) || !dmalloc((void **)&d->d_status, sizeof(uint32_t)) ||
+        !dmalloc((void **)&d->d_iterm, (size_t)T.n_inl * Q * 64 * sizeof(float)))
         return bail(fail(LBM_ERR_OOM, "domain tables"));
     auto up = [&](void *dst, const void *src, size_t n) {
         return copy_sync(d->stream, dst, src, n, hipMemcpyHostToDevice) == hipSuccess;
@@ -523,6 +547,8 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
         !up(d->d_wall, T.wall.data(), T.wall.size() * 4) || !up(d->d_inlet, T.inlet.data(), T.inlet.size() * 4) ||
         !up(d->d_inlrec, T.inlrec.data(), T.inlrec.size() * 4))
         return bail(fail(LBM_ERR_DEVICE, "upload of domain tables failed"));
+    if (build_inlet_terms(d) != hipSuccess)
+        return bail(fail(LBM_ERR_DEVICE, "inlet terms"));
     d->omega = d->omega_b = 1.0 / 0.6;
     d->omega_h = 1.0;
     d->cur = 0;
@@ -673,6 +699,8 @@ int lbm_set_inlet_cells(lbm_domain *d, const float *u_inlet)
         d->graph_dirty = true;
     }
     HIP_TRY(copy_sync(d->stream, d->d_uin, u_inlet, 3 * n * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(build_inlet_terms(d));
+    HIP_TRY(hipStreamSynchronize(d->stream));
     return LBM_OK;
 }
 

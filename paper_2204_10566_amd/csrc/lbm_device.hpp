@@ -2,12 +2,11 @@
 // step (Huang, Noel, Berg, Hosseini, Sec. 2.1 and App. A).
 //
 // One lane updates one cell; one wave (64 lanes) updates one 64-cell tile of
-// the linear cell index.  Populations are structure-of-arrays planes, so the
-// 27 loads and 27 stores of a wave are each one coalesced 64-element access
-// (the loads of the x-moving populations are shifted by one element and
-// straddle one extra cache line, shared with the neighbouring tile).  The
-// whole moment transform runs in registers; the path is HBM-bound, so there
-// is no LDS staging and no MFMA.
+// the linear cell index.  Each tile stores its 27 populations as 27
+// contiguous 64-element rows, so the 27 stores of a wave are full-line
+// writes and each load is one or two contiguous runs.  The whole moment
+// transform runs in registers; the path is HBM-bound, so there is no LDS
+// staging and no MFMA.
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -39,9 +38,10 @@ constexpr uint32_t kWavesPerBlock = LBM_WAVES_PER_BLOCK;
 constexpr uint32_t kBlock = 64 * kWavesPerBlock;
 enum : uint8_t { FL_FLUID = 0, FL_SOLID = 1, FL_INLET = 2, FL_OUTLET = 3 };
 
-// wall-tile link mask: bits 0..26 halfway bounce-back for direction i,
-// bit 30 the cell has moving-wall inlet links (see the inlet mask), bit 31
-// the cell is not updated.
+// wall-tile link mask of a cell: bits 0..26 halfway bounce-back for
+// direction i, bit 30 the cell has moving-wall inlet links, bit 31 the cell
+// is not updated.
+constexpr uint32_t kMaskBB = (1u << Q) - 1;
 constexpr uint32_t kMaskInlet = 1u << 30;
 constexpr uint32_t kMaskSkip = 1u << 31;
 // inlet record of a cell with moving-wall inlet links: word 0 the link mask,
@@ -81,12 +81,9 @@ __host__ __device__ inline uint32_t fdiv(uint32_t n, FastDiv f)
 struct KDomain {
     char *buf[2];            // population buffers, 27 planes of P elements
     const uint32_t *wall;    // link masks of wall tiles, 64 per wall tile
-    const uint32_t *inlet;   // inlet record index per wall-tile cell, same indexing
-    const uint32_t *inlrec;  // inlet records, kRecWords each
-    const float *uin;        // inlet velocity [3][n_inlet] by inlet ordinal, or null
-    uint32_t n_inlet;
+    const float *iterm;      // inlet terms, [27][64] per inlet tile
     uint32_t *status;        // bit 0: a step went unstable
-    uint32_t P;              // cells rounded up to whole tiles (uin plane stride)
+    uint32_t P;              // cells rounded up to whole tiles
     uint32_t tbytes;         // bytes of one tile block: 27 x 64 populations
     uint32_t bufbytes;       // bytes of one population buffer: (P / 64) tile blocks
     uint32_t nx, ny, nz, ncells;
@@ -98,16 +95,17 @@ struct KDomain {
     uint32_t step0, nsteps, cur0, pad;
 };
 
+// One entry of a tile list (32 bytes; a wave reads it with scalar loads).
+// Everything the wave needs to issue its loads is here, so none of them
+// waits for a per-cell table.
 struct TileRec {
-    uint32_t tile;  // tile index: cells [64 tile, 64 tile + 64)
-    int32_t mask;   // wall-tile slot, or -1 for an interior tile
-};
-
-struct BatchTileRec {
-    uint32_t slot;
-    uint32_t tile;
-    int32_t mask;
-    uint32_t pad;
+    uint32_t slot;   // domain slot in a packed launch (0 otherwise)
+    uint32_t tile;   // cells [64 tile, 64 tile + 64)
+    int32_t wall;    // wall-tile slot (per-cell link masks), -1 for an interior tile
+    uint32_t bb;     // union of the cells' bounce-back links
+    uint32_t inl;    // inlet-term block, kNoRec if no cell has an inlet link
+    uint32_t inlm;   // union of the cells' inlet links
+    uint32_t act[2]; // bit l of act[l / 32]: the cell of lane l is updated
 };
 
 // Tile-major population layout: the 27 populations of the 64 cells of a
@@ -144,6 +142,12 @@ template <> struct Storage<ST_FP32> {
     }
     __device__ static float to_f(T v, int) { return v; }
     __device__ static T from_f(float v, int) { return v; }
+    // stored bits, and their value for direction i
+    __device__ static uint32_t raw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LBM_LOAD_AUX);
+    }
+    __device__ static float from_raw(uint32_t b, int) { return __uint_as_float(b); }
 };
 template <> struct Storage<ST_FP16S> {
     using T = _Float16;
@@ -160,6 +164,11 @@ template <> struct Storage<ST_FP16S> {
     __device__ static float to_f(T h, int i) { return __builtin_fmaf((float)h, kFp16InvScale, weight(i)); }
     // conversion to FP16 rounds to nearest even (v_cvt_f16_f32)
     __device__ static T from_f(float v, int i) { return (_Float16)((v - weight(i)) * kFp16Scale); }
+    __device__ static uint32_t raw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LOAD_AUX);
+    }
+    __device__ static float from_raw(uint32_t b, int i) { return to_f(__builtin_bit_cast(_Float16, (uint16_t)b), i); }
 };
 template <> struct Storage<ST_BF16S> {
     using T = uint16_t;
@@ -173,6 +182,11 @@ template <> struct Storage<ST_BF16S> {
         __builtin_amdgcn_raw_buffer_store_b16(from_f(v, i), r, voff, soff, LBM_STORE_AUX);
     }
     __device__ static float to_f(T h, int i) { return __uint_as_float((uint32_t)h << 16) + weight(i); }
+    __device__ static uint32_t raw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LOAD_AUX);
+    }
+    __device__ static float from_raw(uint32_t b, int i) { return to_f((uint16_t)b, i); }
     // round to nearest even on the upper 16 bits (finite inputs)
     __device__ static T from_f(float v, int i)
     {
@@ -305,24 +319,19 @@ __device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega
 // collision, store (Sec. 2.1, Eq. (6); boundary rules of Sec. 2.2).
 // ---------------------------------------------------------------------------
 template <int ST, bool HIGH1>
-__device__ __forceinline__ void update_tile(const KDomain &d, uint32_t tile, int32_t mslot, uint32_t src_idx,
-                                            uint32_t lane)
+__device__ __forceinline__ void update_tile(const KDomain &d, const TileRec &rec, uint32_t src_idx, uint32_t lane)
 {
     using S = Storage<ST>;
     constexpr uint32_t es = S::bytes;
     const auto rs = make_rsrc(d.buf[src_idx], d.bufbytes);
     const auto rd = make_rsrc(d.buf[src_idx ^ 1u], d.bufbytes);
-    const uint32_t lin = tile * 64u + lane;
-    uint32_t m = 0;
-    if (mslot >= 0)
-        m = d.wall[(uint32_t)mslot * 64u + lane];
-    if (lin >= d.ncells || (m & kMaskSkip))
-        return;
+    const uint32_t lin = rec.tile * 64u + lane;
+    const bool active = ((lane < 32u ? rec.act[0] : rec.act[1]) >> (lane & 31u)) & 1u;
 
     // cell coordinates and the source coordinates per velocity component:
     // index 0 is the source of c = -1 (x + 1), 1 of c = 0, 2 of c = +1.
     // Periodic axes wrap; other axes clamp to the box (a clamped source is
-    // either the zero-gradient outlet's or masked as a wall).
+    // either the zero-gradient outlet's or a bounce-back link's).
     const uint32_t q = fdiv(lin, d.dnx);
     const uint32_t x = lin - q * d.nx;
     const uint32_t z = fdiv(q, d.dny);
@@ -347,33 +356,42 @@ __device__ __forceinline__ void update_tile(const KDomain &d, uint32_t tile, int
             row[b + 3 * c] = (sz[c] * d.ny + sy[b]) * d.nx;
 
     float f[Q];
-    if (mslot < 0) {
+    if (rec.wall < 0) {
+        // interior tile: every cell is updated and every link is a pull
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             f[i] = S::load(rs, cell_bytes<es>(row[i / 3] + sx[i % 3], d.tbytes), pop_bytes<es>(i), i);
     } else {
-        // bounce-back links read the opposite population of the cell itself
+        if (!active)
+            return;
+        // Bounce-back links take the cell's own opposite population (+ the
+        // moving-wall term of an inlet link).  The tile entry says which
+        // directions any cell of the tile bounces back; for those the wave
+        // loads both candidates, for the others the own load is given an
+        // offset past the end of the buffer, which returns 0 without a
+        // memory access.  All loads are issued before the per-cell mask is
+        // needed; it selects between stored bits (opposite directions share
+        // their weight, so one conversion serves both candidates).
+        const uint32_t m = d.wall[(uint32_t)rec.wall * 64u + lane];
         const uint32_t self = cell_bytes<es>(lin, d.tbytes);
+        uint32_t p[Q], o[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const uint32_t off = (m & (1u << i)) ? self + pop_bytes<es>(Q - 1 - i)
-                                                 : cell_bytes<es>(row[i / 3] + sx[i % 3], d.tbytes) + pop_bytes<es>(i);
-            f[i] = S::load(rs, off, 0u, i);
-        }
-        if ((m & kMaskInlet) && d.uin) { // without an inlet velocity the inlet is a resting wall
-            // moving-wall bounce-back: + 2 w_i (c_i . u_in) / theta0 with
-            // wall density 1, u_in at the inlet cell the link comes from
-            const uint32_t *rec = d.inlrec + d.inlet[(uint32_t)mslot * 64u + lane] * kRecWords;
-            const uint32_t im = rec[0];
+        for (int i = 0; i < Q; ++i)
+            p[i] = S::raw(rs, cell_bytes<es>(row[i / 3] + sx[i % 3], d.tbytes), pop_bytes<es>(i));
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                if (im & (1u << i)) {
-                    const uint32_t k = rec[1 + i];
-                    const float cu = (float)cx(i) * d.uin[k] + (float)cy(i) * d.uin[d.n_inlet + k] +
-                                     (float)cz(i) * d.uin[2u * d.n_inlet + k];
-                    f[i] += 6.0f * weight(i) * cu;
-                }
-            }
+        for (int i = 0; i < Q; ++i)
+            o[i] = S::raw(rs, ((rec.bb >> i) & 1u) ? self : d.bufbytes, pop_bytes<es>(Q - 1 - i));
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            f[i] = S::from_raw(((m >> i) & 1u) ? o[i] : p[i], i);
+        if (rec.inlm) {
+            // the term block holds 0 for links that are not inlet links
+            constexpr uint32_t kTermBytes = Q * 64u * 4u;
+            const auto rt = make_rsrc((const char *)(d.iterm + (size_t)rec.inl * (Q * 64u)), kTermBytes);
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                f[i] += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                    rt, ((rec.inlm >> i) & 1u) ? lane * 4u : kTermBytes, (uint32_t)i * 256u, 0));
         }
     }
 
@@ -386,6 +404,39 @@ __device__ __forceinline__ void update_tile(const KDomain &d, uint32_t tile, int
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         S::store(rd, own, pop_bytes<es>(i), f[i], i);
+}
+
+// Inlet terms of the inlet tiles: for inlet link i of a cell, the moving-
+// wall term 2 w_i (c_i . u_in) / theta0 with wall density 1 and u_in at the
+// inlet cell the link comes from (Sec. 2.2); 0 for every other link and for
+// every link when no inlet velocity is set.  One wave per tile entry.
+__global__ __launch_bounds__(256) void k_inlet_terms(const TileRec *__restrict__ tiles, uint32_t ntiles,
+                                                     const uint32_t *__restrict__ inlet,
+                                                     const uint32_t *__restrict__ inlrec,
+                                                     const float *__restrict__ uin, uint32_t n_inlet,
+                                                     float *__restrict__ iterm)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
+    if (t >= ntiles)
+        return;
+    const TileRec rec = tiles[t];
+    if (rec.inl == kNoRec)
+        return;
+    const uint32_t r = inlet[(uint32_t)rec.wall * 64u + lane];
+    const uint32_t *R = r == kNoRec ? nullptr : inlrec + (size_t)r * kRecWords;
+    float *out = iterm + (size_t)rec.inl * (Q * 64u) + lane;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        float v = 0.f;
+        if (R && uin && (R[0] & (1u << i))) {
+            const uint32_t k = R[1 + i];
+            const float cu = (float)cx(i) * uin[k] + (float)cy(i) * uin[n_inlet + k] +
+                             (float)cz(i) * uin[2u * n_inlet + k];
+            v = 6.0f * weight(i) * cu;
+        }
+        out[i * 64] = v;
+    }
 }
 
 // Block index -> logical block: consecutive hardware blocks go round-robin
@@ -407,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const Tile
         __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
     for (uint32_t t = w0; t < ntiles; t += nw) {
         const TileRec rec = tiles[t];
-        update_tile<ST, HIGH1>(d, rec.tile, rec.mask, src_idx, lane);
+        update_tile<ST, HIGH1>(d, rec, src_idx, lane);
     }
 }
 
@@ -417,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const Tile
 // says whether it takes part in this step.
 template <int ST, bool HIGH1>
 __global__ __launch_bounds__(kBlock) void k_stream_collide_batched(const KDomain *__restrict__ doms,
-                                                                const BatchTileRec *__restrict__ tiles,
+                                                                const TileRec *__restrict__ tiles,
                                                                 const uint32_t *__restrict__ ctrl)
 {
     const uint32_t lane = threadIdx.x & 63u;
@@ -426,13 +477,13 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide_batched(const KDomain
     const uint32_t w0 =
         __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
     for (uint32_t t = w0; t < ntiles; t += nw) {
-        const BatchTileRec rec = tiles[t];
+        const TileRec rec = tiles[t];
         const KDomain &dd = doms[rec.slot];
         const uint32_t k = g - dd.step0;
         if (k >= dd.nsteps)
             continue;
         const uint32_t s = (dd.cur0 + k) & 1u;
-        update_tile<ST, HIGH1>(dd, rec.tile, rec.mask, s, lane);
+        update_tile<ST, HIGH1>(dd, rec, s, lane);
     }
 }
 
