@@ -7,10 +7,13 @@
  * the update of Sec. 2.1, Eq. (6), with the central Hermite moments of
  * Eqs. (7)-(8), the full (sixth-order) Hermite equilibrium of Eq. (4) and
  * App. A, Eqs. (A.4)-(A.6), relaxation rates as stated after Eq. (8) and in
- * App. A, on the D3Q27 stencil of App. A, Eqs. (A.1)-(A.2); streaming in
- * pull form; halfway bounce-back walls, a moving-wall velocity inlet
- * (profile of Sec. 2.2, Eq. (12)) and a zero-gradient outlet.  Every step of
- * the update runs in the library's own HIP kernels.
+ * App. A, on the D3Q27 stencil of App. A, Eqs. (A.1)-(A.2); halfway
+ * bounce-back walls, a moving-wall velocity inlet (profile of Sec. 2.2,
+ * Eq. (12)) and a zero-gradient outlet.  Each step gives exactly the pull
+ * update (every cell gathers f_i from x - c_i, then collides); the library
+ * runs it in place on a single population array, alternating a streaming
+ * step and a local step so that every step reads and writes the same slots.
+ * Every step of the update runs in the library's own HIP kernels.
  *
  * Conventions
  *   - Every function returns an int status: LBM_OK (0) or a negative
@@ -24,13 +27,15 @@
  *     the axial (inlet-to-outlet) direction.
  *   - Population order: i = (cx+1) + 3(cy+1) + 9(cz+1) for the velocity
  *     c_i = (cx, cy, cz) in {-1,0,1}^3; the opposite of i is 26 - i.
- *   - Populations are stored tile-major: cells are grouped into 64-cell
- *     tiles of the linear index, and the 27 populations of a tile form one
- *     block (population i of the tile's cell l at element 64*i + l of the
- *     block).  P = lbm_plane_stride(...) is ncells rounded up to whole
- *     tiles; a buffer holds 27*P elements.  lbm_get_populations and
- *     lbm_set_populations convert to and from a plain [i][cell] layout.
- *   - The stored state is the post-collision population of the last step.
+ *   - Populations are stored tile-major in one array per domain: cells are
+ *     grouped into 64-cell tiles of the linear index, and the 27 slots of a
+ *     tile form one block (slot k of the tile's cell l at element 64*k + l
+ *     of the block), followed by 2*9*ny*nz outlet side elements
+ *     (lbm_array_bytes).  Between calls the array holds f*_i(x) in slot
+ *     26 - i, or the streamed form after an odd step count; the library
+ *     converts as needed.  lbm_get_populations and lbm_set_populations use a
+ *     plain [i][cell] layout.
+ *   - The state is the post-collision population f* of the last step.
  *   - Calls on one domain are not thread-safe; different domains may be
  *     used from different threads.  All work is issued on the domain's
  *     stream; the calls below return only after that work completed.
@@ -104,27 +109,27 @@ typedef struct lbm_domain_info {
  *   storage      enum lbm_storage.
  *   hip_stream   hipStream_t to issue work on, or NULL for a stream the
  *                library creates.  The stream must outlive the domain.
- * Allocates both population buffers and initialises f = f^eq(1, 0).
- * A domain needs 27*P*sizeof(storage) < 4 GiB.
+ * Allocates the population array and initialises f = f^eq(1, 0).
+ * A domain needs lbm_array_bytes(...) < 4 GiB - 64 KiB.
  * Errors: LBM_ERR_ARG (bad sizes, flags or storage), LBM_ERR_OOM,
  * LBM_ERR_DEVICE.
  */
 int lbm_create_domain(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
                       void *hip_stream, lbm_domain **out);
 
-/* P (in cells) of a domain of nx*ny*nz cells: ncells rounded up to a
- * multiple of 64.  A population buffer holds 27*P elements.  0 for invalid
- * sizes. */
-uint64_t lbm_plane_stride(int nx, int ny, int nz);
+/* Bytes of the population array of a domain of nx*ny*nz cells in the
+ * given storage: 27 slots per cell for ncells rounded up to a multiple of
+ * 64, plus 2*9*ny*nz side elements, rounded up to 256 bytes.  0 for
+ * invalid arguments. */
+uint64_t lbm_array_bytes(int nx, int ny, int nz, int storage);
 
 /*
- * As lbm_create_domain, but adopts two caller-allocated device buffers of
- * 27*P elements each (P = lbm_plane_stride(nx, ny, nz); sizeof(storage)
- * bytes per element, 256-byte aligned), e.g. from torch.  The caller keeps
- * ownership; the buffers must outlive the domain.
+ * As lbm_create_domain, but adopts a caller-allocated device array of
+ * lbm_array_bytes(nx, ny, nz, storage) bytes, 256-byte aligned (e.g. from
+ * torch).  The caller keeps ownership; the array must outlive the domain.
  */
 int lbm_create_domain_ext(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
-                          void *hip_stream, void *f_a, void *f_b, lbm_domain **out);
+                          void *hip_stream, void *f, lbm_domain **out);
 
 /*
  * Relaxation parameters (Sec. 2.1, Eq. (5) and the text after Eq. (8);

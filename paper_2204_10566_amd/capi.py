@@ -49,7 +49,7 @@ SIGNATURES = {
     "lbm_create_domain": (ctypes.c_int, [_u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, ctypes.c_int,
                                          _vp, ctypes.POINTER(_vp)]),
     "lbm_create_domain_ext": (ctypes.c_int, [_u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
-                                             ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+                                             ctypes.c_int, _vp, _vp, ctypes.POINTER(_vp)]),
     "lbm_set_params": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_rates": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_inlet": (ctypes.c_int, [_vp, _fp]),
@@ -71,7 +71,7 @@ SIGNATURES = {
     "lbm_batch_stats": (ctypes.c_int, [_vp, _ip, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                        ctypes.POINTER(ctypes.c_size_t)]),
     "lbm_batch_destroy": (ctypes.c_int, [_vp]),
-    "lbm_plane_stride": (ctypes.c_uint64, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "lbm_array_bytes": (ctypes.c_uint64, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "lbm_selftest_host": (ctypes.c_int, []),
     "lbm_version": (ctypes.c_char_p, []),
 }
@@ -120,7 +120,7 @@ def _f32(a, n=None):
 class Domain:
     """One simulation domain on the current HIP device."""
 
-    def __init__(self, flags, periodic=0, storage="fp32", stream=None, buffers=None):
+    def __init__(self, flags, periodic=0, storage="fp32", stream=None, array=None):
         fl = np.ascontiguousarray(flags, dtype=np.uint8)
         if fl.ndim != 3:
             raise ValueError("flags must be [nz, ny, nx]")
@@ -129,11 +129,11 @@ class Domain:
         st = STORAGE[storage] if isinstance(storage, str) else int(storage)
         h = _vp()
         stream_p = _vp(stream) if stream else None
-        if buffers is None:
+        if array is None:
             check(lbm_create_domain(fl.ctypes.data_as(_u8p), nx, ny, nz, periodic, st, stream_p, ctypes.byref(h)))
         else:
-            check(lbm_create_domain_ext(fl.ctypes.data_as(_u8p), nx, ny, nz, periodic, st, stream_p,
-                                        _vp(buffers[0]), _vp(buffers[1]), ctypes.byref(h)))
+            check(lbm_create_domain_ext(fl.ctypes.data_as(_u8p), nx, ny, nz, periodic, st, stream_p, _vp(array),
+                                        ctypes.byref(h)))
         self.h = h
         self.ncells = nx * ny * nz
 

@@ -66,9 +66,9 @@ bool updated(uint8_t fl) { return fl == LBM_FLUID || fl == LBM_OUTLET; }
 
 // Link classification of one cell (host copy of the boundary rules):
 // returns the wall mask (bit i: halfway bounce-back for population i,
-// kMaskInlet if any link comes from an inlet cell, kMaskSkip if the cell is
-// not updated) and the inlet mask; src[i] receives the inlet cell of each
-// inlet link.
+// kMaskOutlet for an outlet cell, kMaskInlet if any link comes from an inlet
+// cell, kMaskSkip if the cell is not updated) and the inlet mask; src[i]
+// receives the inlet cell of each inlet link.
 void classify_cell(const uint8_t *flags, int nx, int ny, int nz, unsigned per, uint64_t cell, uint32_t &wall,
                    uint32_t &inl, uint64_t *src = nullptr)
 {
@@ -79,6 +79,8 @@ void classify_cell(const uint8_t *flags, int nx, int ny, int nz, unsigned per, u
         wall = kMaskSkip;
         return;
     }
+    if (self == LBM_OUTLET)
+        wall |= kMaskOutlet;
     const int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((uint64_t)nx * ny));
     for (int i = 0; i < Q; ++i) {
         int sx = x - cx(i), sy = y - cy(i), sz = z - cz(i);
@@ -123,7 +125,7 @@ struct Tiles {
 // contiguous tile ranges and concatenated in order.  inlet_cells: the inlet
 // cells in ascending order (their position is the inlet ordinal).
 void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, const std::vector<uint64_t> &inlet_cells,
-                 Tiles &out)
+                 bool outlets, Tiles &out)
 {
     const uint64_t ncells = (uint64_t)nx * ny * nz;
     const uint64_t ntiles = (ncells + 63) / 64;
@@ -138,7 +140,7 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
         uint64_t src[Q];
         for (uint64_t t = t0; t < t1; ++t) {
             bool any = false, plain = true;
-            TileRec r{0u, (uint32_t)t, -1, 0u, kNoRec, 0u, {0u, 0u}};
+            TileRec r{0u, (uint32_t)t, -1, 0u, kNoRec, 0u, {0u, 0u}, 0u, {0u, 0u, 0u}};
             for (int l = 0; l < 64; ++l) {
                 const uint64_t c = t * 64 + l;
                 rec[l] = kNoRec;
@@ -165,6 +167,8 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
                     r.act[l >> 5] |= 1u << (l & 31);
                     r.bb |= wl[l] & kMaskBB;
                     r.inlm |= il[l];
+                    if (outlets && !(per & 1u) && (c % nx) == (uint64_t)nx - 1)
+                        r.edge = 1u;
                 }
                 if (wl[l])
                     plain = false;
@@ -206,7 +210,15 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
     }
 }
 
-constexpr int kGraphSteps = 16; // steps per captured graph (even: ends on the starting buffer)
+constexpr int kGraphSteps = 16; // steps per graph (even: ends in the phase it starts in)
+
+// Bytes of a domain's population array: the tile blocks, then 2 x 9 side
+// rows of ny * nz elements, rounded up to 256 bytes.
+uint64_t array_bytes(uint64_t P, int ny, int nz, int storage)
+{
+    const uint64_t es = storage_bytes(storage);
+    return (Q * P * es + 18ull * ny * nz * es + 255) / 256 * 256;
+}
 
 } // namespace
 
@@ -218,8 +230,10 @@ struct lbm_domain {
     bool own_stream = false;
     bool own_buffers = true;
     int device = 0;
-    char *buf[2] = {nullptr, nullptr};
-    int cur = 0; // buffer holding the current state
+    char *buf = nullptr;  // the population array
+    uint64_t bytes = 0;   // its size
+    int phase = 0;        // phase of the stored state (k_stream_collide)
+    bool outlets = false; // the domain has outlet cells
     uint8_t *d_flags = nullptr;
     TileRec *d_tiles = nullptr;
     uint32_t *d_wall = nullptr, *d_inlet = nullptr, *d_inlrec = nullptr;
@@ -296,14 +310,15 @@ hipError_t copy_sync(hipStream_t s, void *dst, const void *src, size_t n, hipMem
 KDomain kdomain(const lbm_domain *d)
 {
     KDomain k{};
-    k.buf[0] = d->buf[0];
-    k.buf[1] = d->buf[1];
+    k.buf = d->buf;
+    k.flags = d->d_flags;
     k.wall = d->d_wall;
     k.iterm = d->d_iterm;
     k.status = d->d_status;
     k.P = (uint32_t)d->P;
     k.tbytes = (uint32_t)(Q * 64 * storage_bytes(d->storage));
-    k.bufbytes = (uint32_t)(d->P / 64 * k.tbytes);
+    k.side = (uint32_t)(d->P / 64 * k.tbytes);
+    k.bufbytes = (uint32_t)d->bytes;
     k.nx = d->nx;
     k.ny = d->ny;
     k.nz = d->nz;
@@ -340,26 +355,30 @@ uint32_t step_grid(const lbm_domain *d)
 }
 
 template <int ST, bool H>
-hipError_t launch_step_t(const lbm_domain *d, uint32_t src)
+hipError_t launch_step_t(const lbm_domain *d, uint32_t phase)
 {
     const KDomain k = kdomain(d);
-    hipLaunchKernelGGL((k_stream_collide<ST, H>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
-                       (uint32_t)d->ntiles, src);
+    if (phase == 0)
+        hipLaunchKernelGGL((k_stream_collide<ST, H>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
+                           (uint32_t)d->ntiles);
+    else
+        hipLaunchKernelGGL((k_local_collide<ST, H>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
+                           (uint32_t)d->ntiles);
     return hipGetLastError();
 }
 
-hipError_t launch_step(const lbm_domain *d, uint32_t src)
+hipError_t launch_step(const lbm_domain *d, uint32_t phase)
 {
     if (d->ntiles == 0)
         return hipSuccess;
     const bool h1 = d->omega_h == 1.0;
     switch (d->storage) {
     case LBM_FP32:
-        return h1 ? launch_step_t<ST_FP32, true>(d, src) : launch_step_t<ST_FP32, false>(d, src);
+        return h1 ? launch_step_t<ST_FP32, true>(d, phase) : launch_step_t<ST_FP32, false>(d, phase);
     case LBM_FP16S:
-        return h1 ? launch_step_t<ST_FP16S, true>(d, src) : launch_step_t<ST_FP16S, false>(d, src);
+        return h1 ? launch_step_t<ST_FP16S, true>(d, phase) : launch_step_t<ST_FP16S, false>(d, phase);
     default:
-        return h1 ? launch_step_t<ST_BF16S, true>(d, src) : launch_step_t<ST_BF16S, false>(d, src);
+        return h1 ? launch_step_t<ST_BF16S, true>(d, phase) : launch_step_t<ST_BF16S, false>(d, phase);
     }
 }
 
@@ -406,10 +425,8 @@ void free_domain(lbm_domain *d)
     release_graph(d);
     if (d->stream) {
         hipStream_t s = d->stream;
-        if (d->own_buffers) {
-            dfree(s, d->buf[0]);
-            dfree(s, d->buf[1]);
-        }
+        if (d->own_buffers)
+            dfree(s, d->buf);
         dfree(s, d->d_flags);
         dfree(s, d->d_tiles);
         dfree(s, d->d_wall);
@@ -437,18 +454,51 @@ hipError_t build_inlet_terms(const lbm_domain *d)
     return hipGetLastError();
 }
 
-// Both buffers receive the initial state, so that cells no step updates
-// (walls, inlet cells, tile padding) hold defined values in either buffer.
+// First side rows of a phase-0 state (the outlet cells' clamped values).
+hipError_t side_refresh(const lbm_domain *d)
+{
+    if (!d->outlets)
+        return hipSuccess;
+    const KDomain k = kdomain(d);
+    const uint32_t blocks = (uint32_t)(((uint64_t)d->ny * d->nz + 255) / 256);
+    dispatch_storage(d->storage, [&](auto st) {
+        hipLaunchKernelGGL((k_side_refresh<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k);
+    });
+    return hipGetLastError();
+}
+
+// Bring the stored state to phase 0, the form every state access uses.
+hipError_t normalise(lbm_domain *d)
+{
+    if (d->phase == 0)
+        return hipSuccess;
+    if (d->ntiles) {
+        const KDomain k = kdomain(d);
+        const uint32_t blocks = (uint32_t)((d->ntiles + 3) / 4);
+        dispatch_storage(d->storage, [&](auto st) {
+            hipLaunchKernelGGL((k_normalise<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k,
+                               (const TileRec *)d->d_tiles, (uint32_t)d->ntiles);
+        });
+        if (hipError_t e = hipGetLastError())
+            return e;
+        if (hipError_t e = side_refresh(d))
+            return e;
+    }
+    d->phase = 0;
+    return hipSuccess;
+}
+
+// f^eq of the given fields (null: rho = 1, u = 0) in every cell, phase 0.
 int init_eq(lbm_domain *d, const float *rho_dev, const float *u_dev)
 {
     const KDomain k = kdomain(d);
     const uint32_t blocks = (uint32_t)((d->P + 255) / 256);
-    for (uint32_t b = 0; b < 2; ++b)
-        dispatch_storage(d->storage, [&](auto st) {
-            hipLaunchKernelGGL((k_init_eq<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k,
-                               d->d_flags, rho_dev, u_dev, b);
-        });
+    dispatch_storage(d->storage, [&](auto st) {
+        hipLaunchKernelGGL((k_init_eq<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, rho_dev, u_dev);
+    });
     HIP_TRY(hipGetLastError());
+    d->phase = 0;
+    HIP_TRY(side_refresh(d));
     HIP_TRY(hipMemsetAsync(d->d_status, 0, sizeof(uint32_t), d->stream));
     d->unstable = false;
     return LBM_OK;
@@ -458,7 +508,7 @@ int init_eq(lbm_domain *d, const float *rho_dev, const float *u_dev)
 uint64_t plane_stride(uint64_t ncells) { return (ncells + 63) / 64 * 64; }
 
 int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage, void *hip_stream, void *fa,
-           void *fb, lbm_domain **out)
+           lbm_domain **out)
 {
     if (!out)
         return fail(LBM_ERR_ARG, "out is null");
@@ -473,11 +523,14 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
         return fail(LBM_ERR_ARG, "bad periodic mask %u", periodic);
     const uint64_t ncells = (uint64_t)nx * ny * nz;
     const uint64_t P = plane_stride(ncells);
-    const uint64_t bufbytes = (uint64_t)Q * P * storage_bytes(storage);
-    if (bufbytes >= (1ull << 32))
-        return fail(LBM_ERR_ARG, "domain of %llu cells needs %llu bytes per buffer; the limit is 4 GiB",
+    const uint64_t bufbytes = array_bytes(P, ny, nz, storage);
+    // buffer offsets are 32-bit; keep room for the out-of-range offsets of
+    // skipped loads
+    if (bufbytes > (1ull << 32) - (1ull << 16))
+        return fail(LBM_ERR_ARG, "domain of %llu cells needs %llu bytes of populations; the limit is 4 GiB",
                     (unsigned long long)ncells, (unsigned long long)bufbytes);
     std::vector<uint64_t> inlet_cells;
+    bool outlets = false;
     for (uint64_t c = 0; c < ncells; ++c) {
         const uint8_t f = flags[c];
         if (f > LBM_OUTLET)
@@ -487,9 +540,10 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
                         (unsigned long long)c);
         if (f == LBM_INLET)
             inlet_cells.push_back(c);
+        outlets |= f == LBM_OUTLET;
     }
     Tiles T;
-    build_tiles(flags, nx, ny, nz, periodic, inlet_cells, T);
+    build_tiles(flags, nx, ny, nz, periodic, inlet_cells, outlets, T);
 
     lbm_domain *d = new lbm_domain();
     d->nx = nx;
@@ -499,6 +553,8 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     d->periodic = periodic;
     d->ncells = ncells;
     d->P = P;
+    d->bytes = bufbytes;
+    d->outlets = outlets;
     d->ntiles = T.recs.size();
     d->nwall = T.wall.size() / 64;
     d->n_updated = T.n_updated;
@@ -525,15 +581,14 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
         d->device_bytes += n;
         return true;
     };
-    if (fa && fb) {
+    if (fa) {
         d->own_buffers = false;
-        d->buf[0] = (char *)fa;
-        d->buf[1] = (char *)fb;
-        if (((uintptr_t)fa | (uintptr_t)fb) & 255u)
-            return bail(fail(LBM_ERR_ARG, "adopted buffers must be 256-byte aligned"));
-        d->device_bytes += 2 * bufbytes;
-    } else if (!dmalloc((void **)&d->buf[0], bufbytes) || !dmalloc((void **)&d->buf[1], bufbytes)) {
-        return bail(fail(LBM_ERR_OOM, "population buffers (2 x %llu bytes)", (unsigned long long)bufbytes));
+        d->buf = (char *)fa;
+        if ((uintptr_t)fa & 255u)
+            return bail(fail(LBM_ERR_ARG, "an adopted population array must be 256-byte aligned"));
+        d->device_bytes += bufbytes;
+    } else if (!dmalloc((void **)&d->buf, bufbytes)) {
+        return bail(fail(LBM_ERR_OOM, "population array (%llu bytes)", (unsigned long long)bufbytes));
     }
     if (!dmalloc((void **)&d->d_flags, ncells) || !dmalloc((void **)&d->d_tiles, T.recs.size() * sizeof(TileRec)) ||
         !dmalloc((void **)&d->d_wall, T.wall.size() * 4) || !dmalloc((void **)&d->d_inlet, T.inlet.size() * 4) ||
@@ -551,7 +606,6 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
         return bail(fail(LBM_ERR_DEVICE, "inlet terms"));
     d->omega = d->omega_b = 1.0 / 0.6;
     d->omega_h = 1.0;
-    d->cur = 0;
     int rc = init_eq(d, nullptr, nullptr);
     if (rc == LBM_OK && hipStreamSynchronize(d->stream) != hipSuccess)
         rc = fail(LBM_ERR_DEVICE, "initialisation failed");
@@ -576,23 +630,26 @@ hipError_t add_kernel_node(hipGraph_t g, hipGraphNode_t prev, const void *func, 
     return hipGraphAddKernelNode(out, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
 }
 
-template <int ST, bool H> const void *step_kernel_t() { return (const void *)k_stream_collide<ST, H>; }
+template <int ST, bool H> const void *step_kernel_t(uint32_t phase)
+{
+    return phase == 0 ? (const void *)k_stream_collide<ST, H> : (const void *)k_local_collide<ST, H>;
+}
 
-const void *step_kernel(int storage, bool h1)
+const void *step_kernel(int storage, bool h1, uint32_t phase)
 {
     switch (storage) {
     case LBM_FP32:
-        return h1 ? step_kernel_t<ST_FP32, true>() : step_kernel_t<ST_FP32, false>();
+        return h1 ? step_kernel_t<ST_FP32, true>(phase) : step_kernel_t<ST_FP32, false>(phase);
     case LBM_FP16S:
-        return h1 ? step_kernel_t<ST_FP16S, true>() : step_kernel_t<ST_FP16S, false>();
+        return h1 ? step_kernel_t<ST_FP16S, true>(phase) : step_kernel_t<ST_FP16S, false>(phase);
     default:
-        return h1 ? step_kernel_t<ST_BF16S, true>() : step_kernel_t<ST_BF16S, false>();
+        return h1 ? step_kernel_t<ST_BF16S, true>(phase) : step_kernel_t<ST_BF16S, false>(phase);
     }
 }
 
-// Build (not capture) a graph of kGraphSteps chained stream-collide nodes
-// starting from buffer 0; built node by node so that work other threads
-// issue meanwhile cannot interfere.
+// Build (not capture) a graph of kGraphSteps chained step nodes starting in
+// phase 0; built node by node so that work other threads issue meanwhile
+// cannot interfere.
 int build_graph(lbm_domain *d)
 {
     release_graph(d);
@@ -601,11 +658,10 @@ int build_graph(lbm_domain *d)
     KDomain k = kdomain(d);
     const TileRec *tiles = d->d_tiles;
     uint32_t nt = (uint32_t)d->ntiles;
-    const void *fn = step_kernel(d->storage, d->omega_h == 1.0);
     hipGraphNode_t prev = nullptr;
     for (int s = 0; s < kGraphSteps; ++s) {
-        uint32_t src = (uint32_t)(s & 1);
-        void *args[] = {&k, &tiles, &nt, &src};
+        const void *fn = step_kernel(d->storage, d->omega_h == 1.0, (uint32_t)(s & 1));
+        void *args[] = {&k, &tiles, &nt};
         hipGraphNode_t node = nullptr;
         hipError_t e = add_kernel_node(g, prev, fn, step_grid(d), kBlock, args, &node);
         if (e != hipSuccess) {
@@ -631,25 +687,26 @@ const char *lbm_last_error(void) { return g_err.c_str(); }
 
 const char *lbm_version(void) { return "lbm-d3q27-chm gfx950 0.1"; }
 
-uint64_t lbm_plane_stride(int nx, int ny, int nz)
+uint64_t lbm_array_bytes(int nx, int ny, int nz, int storage)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || nx > 65535 || ny > 65535 || nz > 65535)
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 65535 || ny > 65535 || nz > 65535 || storage < LBM_FP32 ||
+        storage > LBM_BF16S)
         return 0;
-    return plane_stride((uint64_t)nx * ny * nz);
+    return array_bytes(plane_stride((uint64_t)nx * ny * nz), ny, nz, storage);
 }
 
 int lbm_create_domain(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
                       void *hip_stream, lbm_domain **out)
 {
-    return create(flags, nx, ny, nz, periodic, storage, hip_stream, nullptr, nullptr, out);
+    return create(flags, nx, ny, nz, periodic, storage, hip_stream, nullptr, out);
 }
 
 int lbm_create_domain_ext(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage,
-                          void *hip_stream, void *f_a, void *f_b, lbm_domain **out)
+                          void *hip_stream, void *f, lbm_domain **out)
 {
-    if (!f_a || !f_b)
-        return fail(LBM_ERR_ARG, "adopted buffers are null");
-    return create(flags, nx, ny, nz, periodic, storage, hip_stream, f_a, f_b, out);
+    if (!f)
+        return fail(LBM_ERR_ARG, "adopted population array is null");
+    return create(flags, nx, ny, nz, periodic, storage, hip_stream, f, out);
 }
 
 int lbm_set_rates(lbm_domain *d, double omega, double omega_bulk, double omega_high)
@@ -698,6 +755,8 @@ int lbm_set_inlet_cells(lbm_domain *d, const float *u_inlet)
         d->device_bytes += 3 * n * sizeof(float);
         d->graph_dirty = true;
     }
+    // a phase-1 state carries the old terms in its bounce-back slots
+    HIP_TRY(normalise(d));
     HIP_TRY(copy_sync(d->stream, d->d_uin, u_inlet, 3 * n * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(build_inlet_terms(d));
     HIP_TRY(hipStreamSynchronize(d->stream));
@@ -758,9 +817,9 @@ int lbm_step(lbm_domain *d, int n)
     if (d->ntiles == 0) // nothing is updated, the state stays as it is
         return LBM_OK;
     int left = n;
-    if (left > 0 && d->cur == 1) {
+    if (left > 0 && d->phase == 1) {
         HIP_TRY(launch_step(d, 1));
-        d->cur = 0;
+        d->phase = 0;
         --left;
     }
     if (left >= kGraphSteps) {
@@ -773,8 +832,8 @@ int lbm_step(lbm_domain *d, int n)
         }
     }
     while (left > 0) {
-        HIP_TRY(launch_step(d, (uint32_t)d->cur));
-        d->cur ^= 1;
+        HIP_TRY(launch_step(d, (uint32_t)d->phase));
+        d->phase ^= 1;
         --left;
     }
     if (int rc = sync_status(d))
@@ -792,11 +851,12 @@ int lbm_get_moments_device(lbm_domain *d, float *rho_dev, float *u_dev)
         return fail(LBM_ERR_ARG, "null output");
     if (d->batch)
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    HIP_TRY(normalise(d));
     const KDomain k = kdomain(d);
     const uint32_t blocks = (uint32_t)((d->ncells + 255) / 256);
     dispatch_storage(d->storage, [&](auto st) {
-        hipLaunchKernelGGL((k_moments<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, d->d_flags,
-                           (uint32_t)d->cur, rho_dev, u_dev);
+        hipLaunchKernelGGL((k_moments<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, rho_dev,
+                           u_dev);
     });
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(d->stream));
@@ -829,14 +889,14 @@ int lbm_get_populations(lbm_domain *d, float *f)
         return fail(LBM_ERR_ARG, "null output");
     if (d->batch)
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    HIP_TRY(normalise(d));
     float *df = nullptr;
     if (dalloc(d->stream, (void **)&df, (size_t)Q * d->ncells * sizeof(float)) != hipSuccess)
         return fail(LBM_ERR_OOM, "staging buffer");
     const KDomain k = kdomain(d);
     const uint32_t blocks = (uint32_t)((d->ncells + 255) / 256);
     dispatch_storage(d->storage, [&](auto st) {
-        hipLaunchKernelGGL((k_export<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k,
-                           (uint32_t)d->cur, df);
+        hipLaunchKernelGGL((k_export<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, df);
     });
     int rc = LBM_OK;
     if (hipGetLastError() != hipSuccess ||
@@ -863,11 +923,12 @@ int lbm_set_populations(lbm_domain *d, const float *f)
     if (rc == LBM_OK) {
         const KDomain k = kdomain(d);
         const uint32_t blocks = (uint32_t)((d->ncells + 255) / 256);
-        for (uint32_t b = 0; b < 2; ++b) // both buffers, as for initialisation
-            dispatch_storage(d->storage, [&](auto st) {
-                hipLaunchKernelGGL((k_import<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, b, df);
-            });
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(d->stream) != hipSuccess)
+        dispatch_storage(d->storage, [&](auto st) {
+            hipLaunchKernelGGL((k_import<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, df);
+        });
+        d->phase = 0;
+        if (hipGetLastError() != hipSuccess || side_refresh(d) != hipSuccess ||
+            hipStreamSynchronize(d->stream) != hipSuccess)
             rc = fail(LBM_ERR_DEVICE, "population import failed");
     }
     dfree(d->stream, df);

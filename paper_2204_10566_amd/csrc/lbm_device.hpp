@@ -39,9 +39,10 @@ constexpr uint32_t kBlock = 64 * kWavesPerBlock;
 enum : uint8_t { FL_FLUID = 0, FL_SOLID = 1, FL_INLET = 2, FL_OUTLET = 3 };
 
 // wall-tile link mask of a cell: bits 0..26 halfway bounce-back for
-// direction i, bit 30 the cell has moving-wall inlet links, bit 31 the cell
-// is not updated.
+// direction i, bit 29 the cell is an outlet cell, bit 30 the cell has
+// moving-wall inlet links, bit 31 the cell is not updated.
 constexpr uint32_t kMaskBB = (1u << Q) - 1;
+constexpr uint32_t kMaskOutlet = 1u << 29;
 constexpr uint32_t kMaskInlet = 1u << 30;
 constexpr uint32_t kMaskSkip = 1u << 31;
 // inlet record of a cell with moving-wall inlet links: word 0 the link mask,
@@ -79,23 +80,25 @@ __host__ __device__ inline uint32_t fdiv(uint32_t n, FastDiv f)
 
 // Everything a kernel needs to update one domain.
 struct KDomain {
-    char *buf[2];            // population buffers, 27 planes of P elements
+    char *buf;               // the population array: P / 64 tile blocks, then the outlet side rows
+    const uint8_t *flags;    // cell flags
     const uint32_t *wall;    // link masks of wall tiles, 64 per wall tile
     const float *iterm;      // inlet terms, [27][64] per inlet tile
     uint32_t *status;        // bit 0: a step went unstable
     uint32_t P;              // cells rounded up to whole tiles
     uint32_t tbytes;         // bytes of one tile block: 27 x 64 populations
-    uint32_t bufbytes;       // bytes of one population buffer: (P / 64) tile blocks
+    uint32_t side;           // byte offset of the side rows: 2 x 9 rows of ny * nz elements
+    uint32_t bufbytes;       // bytes of the whole array
     uint32_t nx, ny, nz, ncells;
     FastDiv dnx, dny;
     uint32_t periodic;
     float omega, omega_b, omega_h;
     // batched execution: the domain takes part in global steps
-    // [step0, step0 + nsteps); its state at step0 is in buf[cur0].
-    uint32_t step0, nsteps, cur0, pad;
+    // [step0, step0 + nsteps), starting in phase ph0.
+    uint32_t step0, nsteps, ph0, pad;
 };
 
-// One entry of a tile list (32 bytes; a wave reads it with scalar loads).
+// One entry of a tile list (48 bytes; a wave reads it with scalar loads).
 // Everything the wave needs to issue its loads is here, so none of them
 // waits for a per-cell table.
 struct TileRec {
@@ -106,6 +109,8 @@ struct TileRec {
     uint32_t inl;    // inlet-term block, kNoRec if no cell has an inlet link
     uint32_t inlm;   // union of the cells' inlet links
     uint32_t act[2]; // bit l of act[l / 32]: the cell of lane l is updated
+    uint32_t edge;   // 1: an updated cell of the tile lies on the outlet plane x = nx - 1
+    uint32_t pad[3];
 };
 
 // Tile-major population layout: the 27 populations of the 64 cells of a
@@ -148,6 +153,10 @@ template <> struct Storage<ST_FP32> {
         return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LBM_LOAD_AUX);
     }
     __device__ static float from_raw(uint32_t b, int) { return __uint_as_float(b); }
+    __device__ static void store_raw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t b)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(b, r, voff, soff, LBM_STORE_AUX);
+    }
 };
 template <> struct Storage<ST_FP16S> {
     using T = _Float16;
@@ -169,6 +178,10 @@ template <> struct Storage<ST_FP16S> {
         return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LOAD_AUX);
     }
     __device__ static float from_raw(uint32_t b, int i) { return to_f(__builtin_bit_cast(_Float16, (uint16_t)b), i); }
+    __device__ static void store_raw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t b)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)b, r, voff, soff, LBM_STORE_AUX);
+    }
 };
 template <> struct Storage<ST_BF16S> {
     using T = uint16_t;
@@ -187,6 +200,10 @@ template <> struct Storage<ST_BF16S> {
         return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LOAD_AUX);
     }
     __device__ static float from_raw(uint32_t b, int i) { return to_f((uint16_t)b, i); }
+    __device__ static void store_raw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t b)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)b, r, voff, soff, LBM_STORE_AUX);
+    }
     // round to nearest even on the upper 16 bits (finite inputs)
     __device__ static T from_f(float v, int i)
     {
@@ -315,95 +332,262 @@ __device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega
 }
 
 // ---------------------------------------------------------------------------
-// One wave updates one 64-cell tile: pull gather with boundary resolution,
-// collision, store (Sec. 2.1, Eq. (6); boundary rules of Sec. 2.2).
+// The step, in place on one population array (Sec. 2.1, Eq. (6); boundary
+// rules of Sec. 2.2).  Steps alternate between two phases, so that each
+// step reads and writes the same 27 slots per cell and no second array is
+// needed; slot (x, k) is population k of cell x in the tile layout.
+//
+//  phase 0, streaming step.  On entry slot (x, k) holds f*_kbar(x), the
+//   post-collision population kbar = 26 - k of x.  Link k of x reads slot
+//   a_k(x) = (x - c_k, kbar), which holds f*_k(x - c_k) = f_k(x) after
+//   streaming; a bounce-back link reads its own slot (x, k) = f*_kbar(x)
+//   (+ the moving-wall term).  After the collision the lane writes
+//   f*_kbar(x) (+ the term) to the same slot a_k(x): that is population
+//   kbar of the downstream cell x - c_k after streaming, or, behind a wall,
+//   population k of x itself.  On exit slot (x, k) holds f_k(x) of the
+//   next step.
+//  phase 1, local step.  The lane reads its own 27 slots (f_k), collides
+//   and writes f*_k to slot (x, kbar).
+//
+// Every slot is read and written by one lane only.  Outlet cells take their
+// clamped upstream values (zero-gradient, c_x = -1 links) from side rows
+// that the local step fills for the cells of the last x plane; in the
+// streaming step those cells also copy those values to the outlet cells
+// they feed, and the outlet cells park their leaving c_x = +1 values in a
+// second side row set, so that a phase-1 state can be turned back into the
+// phase-0 form (k_normalise).
 // ---------------------------------------------------------------------------
-template <int ST, bool HIGH1>
-__device__ __forceinline__ void update_tile(const KDomain &d, const TileRec &rec, uint32_t src_idx, uint32_t lane)
-{
-    using S = Storage<ST>;
-    constexpr uint32_t es = S::bytes;
-    const auto rs = make_rsrc(d.buf[src_idx], d.bufbytes);
-    const auto rd = make_rsrc(d.buf[src_idx ^ 1u], d.bufbytes);
-    const uint32_t lin = rec.tile * 64u + lane;
-    const bool active = ((lane < 32u ? rec.act[0] : rec.act[1]) >> (lane & 31u)) & 1u;
 
-    // cell coordinates and the source coordinates per velocity component:
-    // index 0 is the source of c = -1 (x + 1), 1 of c = 0, 2 of c = +1.
-    // Periodic axes wrap; other axes clamp to the box (a clamped source is
-    // either the zero-gradient outlet's or a bounce-back link's).
-    const uint32_t q = fdiv(lin, d.dnx);
-    const uint32_t x = lin - q * d.nx;
-    const uint32_t z = fdiv(q, d.dny);
-    const uint32_t y = q - z * d.ny;
-    const bool px = d.periodic & 1u, py = d.periodic & 2u, pz = d.periodic & 4u;
+// Cell coordinates and source coordinates per velocity component: index 0
+// is the source of c = -1 (x + 1), 1 of c = 0, 2 of c = +1.  Periodic axes
+// wrap; other axes clamp to the box (a clamped source is the outlet's or
+// belongs to a bounce-back link).  row[b + 3c]: first cell of the source
+// row (cy = b - 1, cz = c - 1).
+struct Coords {
+    uint32_t x, y, z;
     uint32_t sx[3], sy[3], sz[3];
-    sx[1] = x;
-    sx[0] = (x + 1 < d.nx) ? x + 1 : (px ? 0u : x);
-    sx[2] = (x > 0) ? x - 1 : (px ? d.nx - 1 : 0u);
-    sy[1] = y;
-    sy[0] = (y + 1 < d.ny) ? y + 1 : (py ? 0u : y);
-    sy[2] = (y > 0) ? y - 1 : (py ? d.ny - 1 : 0u);
-    sz[1] = z;
-    sz[0] = (z + 1 < d.nz) ? z + 1 : (pz ? 0u : z);
-    sz[2] = (z > 0) ? z - 1 : (pz ? d.nz - 1 : 0u);
-    // first cell of each source row (cy, cz)
     uint32_t row[9];
+};
+
+__device__ __forceinline__ Coords coords(const KDomain &d, uint32_t lin)
+{
+    Coords C;
+    const uint32_t q = fdiv(lin, d.dnx);
+    C.x = lin - q * d.nx;
+    C.z = fdiv(q, d.dny);
+    C.y = q - C.z * d.ny;
+    const bool px = d.periodic & 1u, py = d.periodic & 2u, pz = d.periodic & 4u;
+    C.sx[1] = C.x;
+    C.sx[0] = (C.x + 1 < d.nx) ? C.x + 1 : (px ? 0u : C.x);
+    C.sx[2] = (C.x > 0) ? C.x - 1 : (px ? d.nx - 1 : 0u);
+    C.sy[1] = C.y;
+    C.sy[0] = (C.y + 1 < d.ny) ? C.y + 1 : (py ? 0u : C.y);
+    C.sy[2] = (C.y > 0) ? C.y - 1 : (py ? d.ny - 1 : 0u);
+    C.sz[1] = C.z;
+    C.sz[0] = (C.z + 1 < d.nz) ? C.z + 1 : (pz ? 0u : C.z);
+    C.sz[2] = (C.z > 0) ? C.z - 1 : (pz ? d.nz - 1 : 0u);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            row[b + 3 * c] = (sz[c] * d.ny + sy[b]) * d.nx;
+            C.row[b + 3 * c] = (C.sz[c] * d.ny + C.sy[b]) * d.nx;
+    return C;
+}
+
+__device__ __forceinline__ bool lane_active(const TileRec &rec, uint32_t lane)
+{
+    return ((lane < 32u ? rec.act[0] : rec.act[1]) >> (lane & 31u)) & 1u;
+}
+
+// Byte offset of side row element (h, j, plane cell (y, z)): h = 0 holds
+// f*_k of the last-plane cells for the nine c_x = -1 directions k = 3 j,
+// h = 1 the leaving f*_k of the outlet cells for k = 3 j + 2.
+template <uint32_t ES>
+__device__ __forceinline__ uint32_t side_bytes(const KDomain &d, uint32_t h, uint32_t j, uint32_t y, uint32_t z)
+{
+    return d.side + ((h * 9u + j) * (d.ny * d.nz) + z * d.ny + y) * ES;
+}
+
+// Plane coordinate y + dy wrapped or checked against the box; false if it
+// leaves a non-periodic box.
+__device__ __forceinline__ bool plane_step(uint32_t v, int dv, uint32_t n, bool per, uint32_t &out)
+{
+    int w = (int)v + dv;
+    if (w < 0 || w >= (int)n) {
+        if (!per)
+            return false;
+        w = w < 0 ? w + (int)n : w - (int)n;
+    }
+    out = (uint32_t)w;
+    return true;
+}
+
+__device__ __forceinline__ void check_state(const KDomain &d, float rho, float ux, float uy, float uz)
+{
+    if (!(rho > 0.f) || !(__builtin_fabsf(ux) + __builtin_fabsf(uy) + __builtin_fabsf(uz) < 1e30f))
+        atomicOr(d.status, 1u);
+}
+
+// Inlet term of link k of the lane (0 where link k is not an inlet link).
+__device__ __forceinline__ float inlet_term(const KDomain &d, const TileRec &rec, uint32_t lane, int k)
+{
+    constexpr uint32_t kTermBytes = Q * 64u * 4u;
+    const auto rt = make_rsrc((const char *)(d.iterm + (size_t)rec.inl * (Q * 64u)), kTermBytes);
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rt, ((rec.inlm >> k) & 1u) ? lane * 4u : kTermBytes,
+                                                                (uint32_t)k * 256u, 0));
+}
+
+// Byte offset of slot a_k of the lane whose coordinates are C: the plain
+// neighbour slot, or for a c_x = -1 link of a cell on the outlet plane of
+// an edge tile the side row named by h (0: the clamped upstream value to
+// read, 1: where the leaving value of the opposite direction is parked).
+// On that plane such a link is either the outlet's clamped link or a
+// bounce-back link (a fluid cell there has no source beyond the box), and a
+// bounce-back link uses the lane's own slot instead (selected by the mask).
+template <uint32_t ES>
+__device__ __forceinline__ uint32_t slot_of(const KDomain &d, const Coords &C, int k, bool edge_lane, uint32_t h)
+{
+    if (edge_lane && k % 3 == 0) {
+        const int j = k / 3;
+        return h == 0u ? side_bytes<ES>(d, 0u, (uint32_t)j, C.sy[j % 3], C.sz[j / 3])
+                       : side_bytes<ES>(d, 1u, (uint32_t)(8 - j), C.y, C.z);
+    }
+    return cell_bytes<ES>(C.row[k / 3] + C.sx[k % 3], d.tbytes) + pop_bytes<ES>(Q - 1 - k);
+}
+
+// Phase 0 -> 1.
+template <int ST, bool HIGH1>
+__device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
+{
+    using S = Storage<ST>;
+    constexpr uint32_t es = S::bytes;
+    const auto r = make_rsrc(d.buf, d.bufbytes);
+    const uint32_t lin = rec.tile * 64u + lane;
+    const bool wall = rec.wall >= 0;
+    if (wall && !lane_active(rec, lane))
+        return;
 
     float f[Q];
-    if (rec.wall < 0) {
-        // interior tile: every cell is updated and every link is a pull
+    uint32_t m = 0;
+    {
+        const Coords C = coords(d, lin);
+        if (!wall) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            f[i] = S::load(rs, cell_bytes<es>(row[i / 3] + sx[i % 3], d.tbytes), pop_bytes<es>(i), i);
-    } else {
-        if (!active)
-            return;
-        // Bounce-back links take the cell's own opposite population (+ the
-        // moving-wall term of an inlet link).  The tile entry says which
-        // directions any cell of the tile bounces back; for those the wave
-        // loads both candidates, for the others the own load is given an
-        // offset past the end of the buffer, which returns 0 without a
-        // memory access.  All loads are issued before the per-cell mask is
-        // needed; it selects between stored bits (opposite directions share
-        // their weight, so one conversion serves both candidates).
-        const uint32_t m = d.wall[(uint32_t)rec.wall * 64u + lane];
-        const uint32_t self = cell_bytes<es>(lin, d.tbytes);
-        uint32_t p[Q], o[Q];
+            for (int k = 0; k < Q; ++k)
+                f[k] = S::load(r, cell_bytes<es>(C.row[k / 3] + C.sx[k % 3], d.tbytes), pop_bytes<es>(Q - 1 - k), k);
+        } else {
+            // The tile entry says which directions any cell of the tile
+            // bounces back; for those the wave loads both candidates (for
+            // the others the own load gets an offset past the end of the
+            // array, which returns 0 without a memory access), so that every
+            // load is issued before the per-cell mask arrives; the mask only
+            // selects.  Opposite directions share their weight, so one
+            // conversion serves both candidates.
+            const uint32_t self = cell_bytes<es>(lin, d.tbytes);
+            const bool edge_lane = rec.edge && C.x == d.nx - 1u;
+            m = d.wall[(uint32_t)rec.wall * 64u + lane];
+            uint32_t p[Q], o[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            p[i] = S::raw(rs, cell_bytes<es>(row[i / 3] + sx[i % 3], d.tbytes), pop_bytes<es>(i));
+            for (int k = 0; k < Q; ++k)
+                p[k] = S::raw(r, slot_of<es>(d, C, k, edge_lane, 0u), 0u);
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            o[i] = S::raw(rs, ((rec.bb >> i) & 1u) ? self : d.bufbytes, pop_bytes<es>(Q - 1 - i));
+            for (int k = 0; k < Q; ++k)
+                o[k] = S::raw(r, ((rec.bb >> k) & 1u) ? self : d.bufbytes, pop_bytes<es>(k));
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            f[i] = S::from_raw(((m >> i) & 1u) ? o[i] : p[i], i);
-        if (rec.inlm) {
-            // the term block holds 0 for links that are not inlet links
-            constexpr uint32_t kTermBytes = Q * 64u * 4u;
-            const auto rt = make_rsrc((const char *)(d.iterm + (size_t)rec.inl * (Q * 64u)), kTermBytes);
+            for (int k = 0; k < Q; ++k)
+                f[k] = S::from_raw(((m >> k) & 1u) ? o[k] : p[k], k);
+            if (rec.inlm) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-                f[i] += __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-                    rt, ((rec.inlm >> i) & 1u) ? lane * 4u : kTermBytes, (uint32_t)i * 256u, 0));
+                for (int k = 0; k < Q; ++k)
+                    f[k] += inlet_term(d, rec, lane, k);
+            }
         }
     }
 
     float ux, uy, uz;
     const float rho = collide<HIGH1>(f, d.omega, d.omega_b, d.omega_h, ux, uy, uz);
-    if (!(rho > 0.f) || !(__builtin_fabsf(ux) + __builtin_fabsf(uy) + __builtin_fabsf(uz) < 1e30f))
-        atomicOr(d.status, 1u);
+    check_state(d, rho, ux, uy, uz);
 
-    const uint32_t own = cell_bytes<es>(lin, d.tbytes);
+    // The slot addresses are recomputed rather than kept through the
+    // collision (an opaque copy of the index stops the compiler from
+    // holding them in registers).
+    uint32_t lin2 = lin;
+    asm volatile("" : "+v"(lin2) : "v"(f[0]), "v"(f[13]), "v"(f[26]));
+    const Coords C = coords(d, lin2);
+    const bool edge_lane = rec.edge && C.x == d.nx - 1u;
+    if (edge_lane) {
+        // last-plane cell: hand the clamped values to the outlet cells it
+        // feeds, cell (nx - 1, y + c_y, z + c_z) for direction k = 3 j
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-        S::store(rd, own, pop_bytes<es>(i), f[i], i);
+        for (int j = 0; j < 9; ++j) {
+            const int k = 3 * j;
+            uint32_t ty, tz;
+            if (plane_step(C.y, cy(k), d.ny, d.periodic & 2u, ty) && plane_step(C.z, cz(k), d.nz, d.periodic & 4u, tz)) {
+                const uint32_t t = (tz * d.ny + ty) * d.nx + d.nx - 1u;
+                if (d.flags[t] == FL_OUTLET)
+                    S::store(r, cell_bytes<es>(t, d.tbytes), pop_bytes<es>(k), f[k], k);
+            }
+        }
+    }
+    if (rec.inlm) {
+        // bounce-back slots of inlet links carry the term into the next step
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            f[Q - 1 - k] += inlet_term(d, rec, lane, k);
+    }
+    // Each store address is formed just before its store (the opaque copy
+    // of the row index, ordered after the previous store, keeps the
+    // compiler from forming all 27 at once).
+    if (!wall) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            uint32_t rowk = C.row[k / 3];
+            asm volatile("" : "+v"(rowk)::"memory");
+            S::store(r, cell_bytes<es>(rowk + C.sx[k % 3], d.tbytes), pop_bytes<es>(Q - 1 - k), f[Q - 1 - k], k);
+        }
+    } else {
+        const uint32_t self = cell_bytes<es>(lin2, d.tbytes);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            Coords Ck = C;
+            asm volatile("" : "+v"(Ck.row[k / 3])::"memory");
+            S::store(r, ((m >> k) & 1u) ? self + pop_bytes<es>(k) : slot_of<es>(d, Ck, k, edge_lane, 1u), 0u,
+                     f[Q - 1 - k], k);
+        }
+    }
+}
+
+// Phase 1 -> 0.
+template <int ST, bool HIGH1>
+__device__ __forceinline__ void local_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
+{
+    using S = Storage<ST>;
+    constexpr uint32_t es = S::bytes;
+    const auto r = make_rsrc(d.buf, d.bufbytes);
+    if (rec.wall >= 0 && !lane_active(rec, lane))
+        return;
+    const uint32_t lin = rec.tile * 64u + lane;
+    const uint32_t self = cell_bytes<es>(lin, d.tbytes);
+    float f[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+        f[k] = S::load(r, self, pop_bytes<es>(k), k);
+    float ux, uy, uz;
+    const float rho = collide<HIGH1>(f, d.omega, d.omega_b, d.omega_h, ux, uy, uz);
+    check_state(d, rho, ux, uy, uz);
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+        S::store(r, self, pop_bytes<es>(Q - 1 - k), f[k], k);
+    if (rec.edge) {
+        const uint32_t q = fdiv(lin, d.dnx);
+        if (lin - q * d.nx == d.nx - 1u) {
+            // last-plane cell: its c_x = -1 values for the outlet cells
+            const uint32_t z = fdiv(q, d.dny), y = q - z * d.ny;
+#pragma unroll
+            for (int j = 0; j < 9; ++j)
+                S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, f[3 * j], 3 * j);
+        }
+    }
 }
 
 // Inlet terms of the inlet tiles: for inlet link i of a cell, the moving-
@@ -445,27 +629,38 @@ __global__ __launch_bounds__(256) void k_inlet_terms(const TileRec *__restrict__
 // of 8.
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) { return (b & 7u) * (G >> 3) + (b >> 3); }
 
-// Single-domain step.  Each wave takes whole tiles, walking the tile list
-// with a stride of the grid's wave count (one pass when the grid covers
-// every tile).
+// Single-domain steps, one kernel per phase (the local step needs far fewer
+// registers than the streaming step).  Each wave takes whole tiles, walking
+// the tile list with a stride of the grid's wave count (one pass when the
+// grid covers every tile).
 template <int ST, bool HIGH1>
 __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const TileRec *__restrict__ tiles,
-                                                           uint32_t ntiles, uint32_t src_idx)
+                                                           uint32_t ntiles)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t nw = gridDim.x * kWavesPerBlock;
     const uint32_t w0 =
         __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
-    for (uint32_t t = w0; t < ntiles; t += nw) {
-        const TileRec rec = tiles[t];
-        update_tile<ST, HIGH1>(d, rec, src_idx, lane);
-    }
+    for (uint32_t t = w0; t < ntiles; t += nw)
+        stream_tile<ST, HIGH1>(d, tiles[t], lane);
+}
+
+template <int ST, bool HIGH1>
+__global__ __launch_bounds__(kBlock) void k_local_collide(KDomain d, const TileRec *__restrict__ tiles,
+                                                          uint32_t ntiles)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nw = gridDim.x * kWavesPerBlock;
+    const uint32_t w0 =
+        __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
+    for (uint32_t t = w0; t < ntiles; t += nw)
+        local_tile<ST, HIGH1>(d, tiles[t], lane);
 }
 
 // Packed multi-domain step.  ctrl[0] = number of tile records, ctrl[1] =
 // global step.  One wave per tile record (the host keeps the grid at least
 // as large as the table); each tile belongs to one domain, whose descriptor
-// says whether it takes part in this step.
+// says whether, and in which phase, it takes part in this step.
 template <int ST, bool HIGH1>
 __global__ __launch_bounds__(kBlock) void k_stream_collide_batched(const KDomain *__restrict__ doms,
                                                                 const TileRec *__restrict__ tiles,
@@ -482,8 +677,10 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide_batched(const KDomain
         const uint32_t k = g - dd.step0;
         if (k >= dd.nsteps)
             continue;
-        const uint32_t s = (dd.cur0 + k) & 1u;
-        update_tile<ST, HIGH1>(dd, rec, s, lane);
+        if (((dd.ph0 + k) & 1u) == 0u)
+            stream_tile<ST, HIGH1>(dd, rec, lane);
+        else
+            local_tile<ST, HIGH1>(dd, rec, lane);
     }
 }
 
@@ -493,13 +690,77 @@ __global__ void k_advance_step(uint32_t *ctrl)
         ctrl[1] = ctrl[1] + 1u;
 }
 
+// ---------------------------------------------------------------------------
+// State access.  Outside a step the host keeps a domain in phase 0, where
+// population i of cell x, f*_i(x), is slot (x, 26 - i).
+// ---------------------------------------------------------------------------
+
+// Phase 1 -> 0 without a collision: every slot pair (x, k) / a_k(x) of a
+// link that is neither bounced back nor clamped swaps its two values; a
+// bounce-back slot loses its inlet term; the clamped slots of an outlet
+// cell take the leaving values parked in the second side rows.  The first
+// side rows are refreshed afterwards (k_side_refresh).
+template <int ST>
+__global__ __launch_bounds__(256) void k_normalise(KDomain d, const TileRec *__restrict__ tiles, uint32_t ntiles)
+{
+    using S = Storage<ST>;
+    constexpr uint32_t es = S::bytes;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
+    if (t >= ntiles)
+        return;
+    const TileRec rec = tiles[t];
+    if (rec.wall >= 0 && !lane_active(rec, lane))
+        return;
+    const auto r = make_rsrc(d.buf, d.bufbytes);
+    const uint32_t lin = rec.tile * 64u + lane;
+    const Coords C = coords(d, lin);
+    const uint32_t self = cell_bytes<es>(lin, d.tbytes);
+    const uint32_t m = rec.wall >= 0 ? d.wall[(uint32_t)rec.wall * 64u + lane] : 0u;
+    const bool edge_lane = rec.edge && C.x == d.nx - 1u;
+    for (int k = 0; k < Q; ++k) {
+        if ((m >> k) & 1u) {
+            if ((rec.inlm >> k) & 1u) {
+                const float v = S::load(r, self, pop_bytes<es>(k), k) - inlet_term(d, rec, lane, k);
+                S::store(r, self, pop_bytes<es>(k), v, k);
+            }
+        } else if (edge_lane && k % 3 == 0) {
+            S::store_raw(r, self + pop_bytes<es>(k), 0u, S::raw(r, slot_of<es>(d, C, k, true, 1u), 0u));
+        } else if (k > Q / 2) {
+            const uint32_t ak = cell_bytes<es>(C.row[k / 3] + C.sx[k % 3], d.tbytes) + pop_bytes<es>(Q - 1 - k);
+            const uint32_t u = S::raw(r, self + pop_bytes<es>(k), 0u), v = S::raw(r, ak, 0u);
+            S::store_raw(r, self + pop_bytes<es>(k), 0u, v);
+            S::store_raw(r, ak, 0u, u);
+        }
+    }
+}
+
+// First side rows from a phase-0 state: f*_k of each updated last-plane
+// cell for k = 3 j, i.e. slot (x, 26 - 3 j).  One lane per (y, z).
+template <int ST>
+__global__ __launch_bounds__(256) void k_side_refresh(KDomain d)
+{
+    using S = Storage<ST>;
+    constexpr uint32_t es = S::bytes;
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= d.ny * d.nz)
+        return;
+    const uint32_t z = p / d.ny, y = p - z * d.ny;
+    const uint32_t c = (z * d.ny + y) * d.nx + d.nx - 1u;
+    if (d.flags[c] != FL_FLUID && d.flags[c] != FL_OUTLET)
+        return;
+    const auto r = make_rsrc(d.buf, d.bufbytes);
+    const uint32_t cb = cell_bytes<es>(c, d.tbytes);
+    for (int j = 0; j < 9; ++j)
+        S::store_raw(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, S::raw(r, cb + pop_bytes<es>(Q - 1 - 3 * j), 0u));
+}
+
 // f = f^eq(rho, u) in product form: the sixth-order Hermite equilibrium of
 // Eq. (4) factorises into rho prod_a phi(c_a, u_a), phi(0, u) = 2/3 - u^2,
-// phi(+-1, u) = (1 +- 3u + 3u^2)/6 (App. A, Eqs. (A.2)-(A.4)).
+// phi(+-1, u) = (1 +- 3u + 3u^2)/6 (App. A, Eqs. (A.2)-(A.4)).  Written in
+// the phase-0 form; cells that are not updated get the rest state.
 template <int ST>
-__global__ __launch_bounds__(256) void k_init_eq(KDomain d, const uint8_t *__restrict__ flags,
-                                                 const float *__restrict__ rho, const float *__restrict__ u,
-                                                 uint32_t dst_idx)
+__global__ __launch_bounds__(256) void k_init_eq(KDomain d, const float *__restrict__ rho, const float *__restrict__ u)
 {
     using S = Storage<ST>;
     constexpr uint32_t es = S::bytes;
@@ -509,7 +770,7 @@ __global__ __launch_bounds__(256) void k_init_eq(KDomain d, const uint8_t *__res
     float r = 1.f, v[3] = {0.f, 0.f, 0.f};
     bool upd = false;
     if (c < d.ncells) {
-        upd = flags[c] == FL_FLUID || flags[c] == FL_OUTLET;
+        upd = d.flags[c] == FL_FLUID || d.flags[c] == FL_OUTLET;
         if (upd) {
             if (rho)
                 r = rho[c];
@@ -528,34 +789,30 @@ __global__ __launch_bounds__(256) void k_init_eq(KDomain d, const uint8_t *__res
         phi[a][1] = 2.0f / 3.0f - w2;
         phi[a][2] = (1.f + 3.f * w + 3.f * w2) * (1.0f / 6.0f);
     }
+    const auto rr = make_rsrc(d.buf, d.bufbytes);
     const uint32_t cb = cell_bytes<es>(c, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float fe = upd ? r * phi[0][i % 3] * phi[1][(i / 3) % 3] * phi[2][i / 9] : weight(i);
-        *(typename S::T *)(d.buf[dst_idx] + cb + pop_bytes<es>(i)) = S::from_f(fe, i);
+        S::store(rr, cb, pop_bytes<es>(Q - 1 - i), fe, i);
     }
 }
 
-template <int ST> __device__ __forceinline__ const typename Storage<ST>::T *pop_at(const char *buf, uint32_t cb, int i)
-{
-    return (const typename Storage<ST>::T *)(buf + cb + pop_bytes<Storage<ST>::bytes>(i));
-}
-
-// Density and velocity of the stored state at updated cells.
+// Density and velocity of a phase-0 state at updated cells (0 elsewhere).
 template <int ST>
-__global__ __launch_bounds__(256) void k_moments(KDomain d, const uint8_t *__restrict__ flags, uint32_t cur,
-                                                 float *__restrict__ rho, float *__restrict__ u)
+__global__ __launch_bounds__(256) void k_moments(KDomain d, float *__restrict__ rho, float *__restrict__ u)
 {
     using S = Storage<ST>;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.ncells)
         return;
     float r = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-    if (flags[c] == FL_FLUID || flags[c] == FL_OUTLET) {
+    if (d.flags[c] == FL_FLUID || d.flags[c] == FL_OUTLET) {
+        const auto rr = make_rsrc(d.buf, d.bufbytes);
         const uint32_t cb = cell_bytes<S::bytes>(c, d.tbytes);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float fi = S::to_f(*pop_at<ST>(d.buf[cur], cb, i), i);
+            const float fi = S::load(rr, cb, pop_bytes<S::bytes>(Q - 1 - i), i);
             r += fi;
             jx += (float)cx(i) * fi;
             jy += (float)cy(i) * fi;
@@ -572,31 +829,33 @@ __global__ __launch_bounds__(256) void k_moments(KDomain d, const uint8_t *__res
     u[2u * d.ncells + c] = jz;
 }
 
-// Stored populations <-> FP32 values of f_i, layout [i][cell] without padding.
+// Phase-0 state <-> FP32 values of f_i, layout [i][cell] without padding.
 template <int ST>
-__global__ __launch_bounds__(256) void k_export(KDomain d, uint32_t cur, float *__restrict__ out)
+__global__ __launch_bounds__(256) void k_export(KDomain d, float *__restrict__ out)
 {
     using S = Storage<ST>;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.ncells)
         return;
+    const auto rr = make_rsrc(d.buf, d.bufbytes);
     const uint32_t cb = cell_bytes<S::bytes>(c, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        out[(size_t)i * d.ncells + c] = S::to_f(*pop_at<ST>(d.buf[cur], cb, i), i);
+        out[(size_t)i * d.ncells + c] = S::load(rr, cb, pop_bytes<S::bytes>(Q - 1 - i), i);
 }
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_import(KDomain d, uint32_t cur, const float *__restrict__ in)
+__global__ __launch_bounds__(256) void k_import(KDomain d, const float *__restrict__ in)
 {
     using S = Storage<ST>;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.ncells)
         return;
+    const auto rr = make_rsrc(d.buf, d.bufbytes);
     const uint32_t cb = cell_bytes<S::bytes>(c, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        *(typename S::T *)(d.buf[cur] + cb + pop_bytes<S::bytes>(i)) = S::from_f(in[(size_t)i * d.ncells + c], i);
+        S::store(rr, cb, pop_bytes<S::bytes>(Q - 1 - i), in[(size_t)i * d.ncells + c], i);
 }
 
 } // namespace lbm

@@ -235,20 +235,19 @@ def test_unstable_run_reports_error(capi):
     assert d.step_status(3) == capi.OK
 
 
-def test_adopted_torch_buffers_and_stream(capi, orc):
-    """Population buffers and the stream come from torch."""
+def test_adopted_torch_array_and_stream(capi, orc):
+    """The population array and the stream come from torch."""
     import torch
 
     n = 16
     fl = I.periodic_box(n)
     u0 = I.taylor_green_velocity(n, n, n, 0.03).astype(np.float32)
-    P = int(capi.lbm_plane_stride(n, n, n))
-    assert P >= fl.size and P % 64 == 0
-    a = torch.empty(27 * P, dtype=torch.float32, device="cuda")
-    b = torch.empty(27 * P, dtype=torch.float32, device="cuda")
+    nbytes = int(capi.lbm_array_bytes(n, n, n, capi.FP32))
+    assert nbytes >= 27 * 4 * fl.size and nbytes % 256 == 0
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     s = torch.cuda.Stream()
-    say("torch-adopted buffers 16^3")
-    d = capi.Domain(fl, periodic=7, storage="fp32", stream=s.cuda_stream, buffers=(a.data_ptr(), b.data_ptr()))
+    say("torch-adopted array 16^3")
+    d = capi.Domain(fl, periodic=7, storage="fp32", stream=s.cuda_stream, array=a.data_ptr())
     d.set_params(0.7)
     d.init_fields(None, u0)
     d.step(20)
@@ -261,3 +260,44 @@ def test_adopted_torch_buffers_and_stream(capi, orc):
     _, uo = orc.moments(fl, f)
     assert rel_l2(ug, uo) <= 1e-5
     d.destroy()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_state_access_between_odd_and_even_steps(capi, orc, storage):
+    """The library runs steps in place, alternating two phases.  Reading the
+    state after an odd number of steps, changing the inlet velocity there
+    and stepping on must equal the pull update of the oracle: 3 steps,
+    export, 1 step, new inlet velocity, 3 steps, export."""
+    fl = mixed_geometry()
+    rng = np.random.default_rng(21)
+    n_in = int((fl == I.INLET).sum())
+    uin1 = np.zeros((3,) + fl.shape, np.float32)
+    uin1[:, fl == I.INLET] = 0.03 * rng.uniform(-1, 1, (3, n_in))
+    uin2 = np.zeros((3,) + fl.shape, np.float32)
+    uin2[:, fl == I.INLET] = 0.03 * rng.uniform(-1, 1, (3, n_in))
+    f0 = random_pops(orc, fl, 13)
+    rates = (1 / 0.57, 1.1, 1.2)
+    rv = orc.rates_vector(*rates)
+    upd = updated(fl)
+    tol = 4e-7 if storage == "fp32" else 2e-3
+    say(f"odd/even state access {storage}")
+    d = capi.Domain(fl, periodic=4, storage=storage)
+    d.set_rates(*rates)
+    d.set_inlet(uin1)
+    d.set_populations(f0)
+    f0 = d.populations().astype(np.float64)  # the stored (rounded) start
+    d.step(3)
+    st, fo = orc.step(fl, f0, rv, 3, periodic=4, uin=uin1)
+    assert st == 0
+    assert np.abs(d.populations()[:, upd] - fo[:, upd]).max() <= 3 * tol
+    d.step(1)
+    d.set_inlet(uin2)
+    d.step(3)
+    st, fo = orc.step(fl, fo, rv, 1, periodic=4, uin=uin1)
+    st, fo = orc.step(fl, fo, rv, 3, periodic=4, uin=uin2)
+    err = np.abs(d.populations()[:, upd] - fo[:, upd]).max()
+    say(f"  max abs err {err:.3e}")
+    assert err <= 7 * tol
+    rg, ug = d.moments()
+    ro, uo = orc.moments(fl, fo)
+    assert np.abs(ug - uo)[:, upd].max() <= 7 * tol * 30
