@@ -210,7 +210,10 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
     }
 }
 
-constexpr int kGraphSteps = 16; // steps per graph (even: ends in the phase it starts in)
+#ifndef LBM_GRAPH_STEPS
+#define LBM_GRAPH_STEPS 64
+#endif
+constexpr int kGraphSteps = LBM_GRAPH_STEPS; // steps per graph (even: ends in the phase it starts in)
 
 // Bytes of a domain's population array: the tile blocks, then 2 x 9 side
 // rows of ny * nz elements, rounded up to 256 bytes.
@@ -334,24 +337,13 @@ KDomain kdomain(const lbm_domain *d)
 
 uint32_t grid8(uint64_t blocks) { return (uint32_t)((blocks + 7) / 8 * 8); }
 
-// Grid of the single-domain kernel: one wave per tile, or at most
-// LBM_GRID_BLOCKS_PER_CU resident blocks per compute unit looping over
-// the tiles when that constant is set.
-#ifndef LBM_GRID_BLOCKS_PER_CU
-#define LBM_GRID_BLOCKS_PER_CU 0
-#endif
-
-uint32_t step_grid(const lbm_domain *d)
+// Grid of the single-domain kernels: one wave per tile (a wave's loads and
+// collision do not overlap within the wave, and tiles per wave beyond one
+// measured slower).
+uint32_t step_grid(const lbm_domain *d, uint32_t phase)
 {
-    uint64_t blocks = (d->ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (LBM_GRID_BLOCKS_PER_CU > 0) {
-        static int cus = 0;
-        if (!cus && (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d->device) != hipSuccess ||
-                     cus <= 0))
-            cus = 256;
-        blocks = std::min<uint64_t>(blocks, (uint64_t)cus * LBM_GRID_BLOCKS_PER_CU);
-    }
-    return grid8(blocks);
+    (void)phase;
+    return grid8((d->ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
 template <int ST, bool H>
@@ -359,10 +351,10 @@ hipError_t launch_step_t(const lbm_domain *d, uint32_t phase)
 {
     const KDomain k = kdomain(d);
     if (phase == 0)
-        hipLaunchKernelGGL((k_stream_collide<ST, H>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
+        hipLaunchKernelGGL((k_stream_collide<ST, H>), dim3(step_grid(d, 0)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
                            (uint32_t)d->ntiles);
     else
-        hipLaunchKernelGGL((k_local_collide<ST, H>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
+        hipLaunchKernelGGL((k_local_collide<ST, H>), dim3(step_grid(d, 1)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
                            (uint32_t)d->ntiles);
     return hipGetLastError();
 }
@@ -663,7 +655,7 @@ int build_graph(lbm_domain *d)
         const void *fn = step_kernel(d->storage, d->omega_h == 1.0, (uint32_t)(s & 1));
         void *args[] = {&k, &tiles, &nt};
         hipGraphNode_t node = nullptr;
-        hipError_t e = add_kernel_node(g, prev, fn, step_grid(d), kBlock, args, &node);
+        hipError_t e = add_kernel_node(g, prev, fn, step_grid(d, (uint32_t)(s & 1)), kBlock, args, &node);
         if (e != hipSuccess) {
             (void)hipGraphDestroy(g);
             return fail(LBM_ERR_DEVICE, "graph node: %s", hipGetErrorString(e));
@@ -952,6 +944,7 @@ int lbm_domain_get_info(const lbm_domain *d, lbm_domain_info *info)
     info->n_inlet = d->inlet_cells.size();
     info->device_bytes = d->device_bytes;
     info->bytes_per_cell_update = 2ull * Q * storage_bytes(d->storage);
+
     return LBM_OK;
 }
 

@@ -226,9 +226,85 @@ template <> struct Storage<ST_BF16S> {
 // central moments of f^eq are (rho, 0, ..., 0) (App. A, Eqs. (A.5)-(A.6)),
 // so relaxing towards it scales each non-conserved moment by (1 - rate).
 // ---------------------------------------------------------------------------
-template <bool HIGH1>
-__device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega_b, float omega_h, float &ux,
-                                         float &uy, float &uz)
+// Collision with omega_high = 1: every central moment of order >= 3 is set
+// to zero, so the post-collision state depends only on rho, u and the six
+// second-order central moments.  Those come straight from raw sums of f
+// (M_ab = S_ab - rho u_a u_b - theta0 rho delta_ab, S_ab = sum c_a c_b f),
+// without the full forward transform; the first-order central moments are
+// zero by definition of u.  The inverse is the same three sweeps as below,
+// over the ten moments that are left.
+__device__ __forceinline__ float collide_h1(float (&f)[Q], float omega, float omega_b, float &ux, float &uy,
+                                            float &uz)
+{
+    // per (c_y, c_z) row t = b + 3c: s0 = sum over c_x, s1 = first, s2 = second moment in x
+    float s0[9], s1[9], s2[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const float A = f[3 * t], B = f[3 * t + 1], C = f[3 * t + 2];
+        s0[t] = A + B + C;
+        s1[t] = C - A;
+        s2[t] = C + A;
+    }
+    float rho = 0.f, jx = 0.f, sxx = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        rho += s0[t];
+        jx += s1[t];
+        sxx += s2[t];
+    }
+    // rows with c_y = -1: t = 3c; c_y = +1: t = 2 + 3c; c_z = -1: t = b; c_z = +1: t = b + 6
+    float jy = 0.f, syy = 0.f, sxy = 0.f, jz = 0.f, szz = 0.f, sxz = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        jy += s0[2 + 3 * c] - s0[3 * c];
+        syy += s0[2 + 3 * c] + s0[3 * c];
+        sxy += s1[2 + 3 * c] - s1[3 * c];
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        jz += s0[b + 6] - s0[b];
+        szz += s0[b + 6] + s0[b];
+        sxz += s1[b + 6] - s1[b];
+    }
+    const float syz = (s0[8] + s0[0]) - (s0[6] + s0[2]);
+    const float inv = __builtin_amdgcn_rcpf(rho);
+    ux = jx * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+    // central second-order Hermite moments, relaxed: off-diagonal and
+    // deviator at omega, trace at omega_b (Sec. 2.1 after Eq. (8))
+    const float ks = 1.f - omega, kb = 1.f - omega_b;
+    const float tr0 = kTheta0 * rho;
+    float mxx = __builtin_fmaf(-jx, ux, sxx) - tr0;
+    float myy = __builtin_fmaf(-jy, uy, syy) - tr0;
+    float mzz = __builtin_fmaf(-jz, uz, szz) - tr0;
+    const float mxy = ks * __builtin_fmaf(-jx, uy, sxy);
+    const float mxz = ks * __builtin_fmaf(-jx, uz, sxz);
+    const float myz = ks * __builtin_fmaf(-jy, uz, syz);
+    {
+        const float d = (kb - ks) * ((mxx + myy + mzz) * (1.0f / 3.0f));
+        mxx = __builtin_fmaf(ks, mxx, d);
+        myy = __builtin_fmaf(ks, myy, d);
+        mzz = __builtin_fmaf(ks, mzz, d);
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+        f[k] = 0.f;
+    f[0] = rho;
+    f[2] = mxx;
+    f[6] = myy;
+    f[18] = mzz;
+    f[4] = mxy;
+    f[10] = mxz;
+    f[12] = myz;
+    return rho;
+}
+
+// Forward central-Hermite transform and relaxation for a general omega_high:
+// three sweeps of the 1-D map (x raw, then shifted to the central moments
+// about ux; y and z directly central), then the relaxation.
+__device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float omega_b, float omega_h, float &ux,
+                                               float &uy, float &uz)
 {
     // x sweep, raw: s0 = sum, s1 = first moment, s2 = second moment
 #pragma unroll
@@ -300,8 +376,16 @@ __device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega
     constexpr int high[17] = {5, 7, 8, 11, 13, 14, 15, 16, 17, 19, 20, 21, 22, 23, 24, 25, 26};
 #pragma unroll
     for (int k = 0; k < 17; ++k)
-        f[high[k]] = HIGH1 ? 0.f : f[high[k]] * kh;
+        f[high[k]] *= kh;
+    return rho;
+}
 
+template <bool HIGH1>
+__device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega_b, float omega_h, float &ux,
+                                         float &uy, float &uz)
+{
+    const float rho = HIGH1 ? collide_h1(f, omega, omega_b, ux, uy, uz)
+                            : moments_relax(f, omega, omega_b, omega_h, ux, uy, uz);
     // inverse sweeps z, y, x: raw moments R0 = m0, R1 = m1 + u m0,
     // R2 = m2 + 2 u m1 + (u^2 + theta0) m0; then f(+1) = (R2 + R1)/2,
     // f(-1) = (R2 - R1)/2, f(0) = R0 - R2.
@@ -455,9 +539,10 @@ __device__ __forceinline__ uint32_t slot_of(const KDomain &d, const Coords &C, i
     return cell_bytes<ES>(C.row[k / 3] + C.sx[k % 3], d.tbytes) + pop_bytes<ES>(Q - 1 - k);
 }
 
-// Phase 0 -> 1.
-template <int ST, bool HIGH1>
-__device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
+// Phase 0 -> 1.  EDGE: the tile has cells on the outlet plane (tile entry
+// `edge`); the other tiles compile without the outlet handling.
+template <int ST, bool HIGH1, bool EDGE>
+__device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     using S = Storage<ST>;
     constexpr uint32_t es = S::bytes;
@@ -484,7 +569,7 @@ __device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec
             // selects.  Opposite directions share their weight, so one
             // conversion serves both candidates.
             const uint32_t self = cell_bytes<es>(lin, d.tbytes);
-            const bool edge_lane = rec.edge && C.x == d.nx - 1u;
+            const bool edge_lane = EDGE && C.x == d.nx - 1u;
             m = d.wall[(uint32_t)rec.wall * 64u + lane];
             uint32_t p[Q], o[Q];
 #pragma unroll
@@ -514,7 +599,7 @@ __device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec
     uint32_t lin2 = lin;
     asm volatile("" : "+v"(lin2) : "v"(f[0]), "v"(f[13]), "v"(f[26]));
     const Coords C = coords(d, lin2);
-    const bool edge_lane = rec.edge && C.x == d.nx - 1u;
+    const bool edge_lane = EDGE && C.x == d.nx - 1u;
     if (edge_lane) {
         // last-plane cell: hand the clamped values to the outlet cells it
         // feeds, cell (nx - 1, y + c_y, z + c_z) for direction k = 3 j
@@ -557,21 +642,46 @@ __device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec
     }
 }
 
-// Phase 1 -> 0.
 template <int ST, bool HIGH1>
-__device__ __forceinline__ void local_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
+__device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
+{
+    if (rec.edge)
+        stream_tile_t<ST, HIGH1, true>(d, rec, lane);
+    else
+        stream_tile_t<ST, HIGH1, false>(d, rec, lane);
+}
+
+// Phase 1 -> 0, in two halves so that a wave can issue the loads of its
+// next tile before it collides the current one.  Lanes of cells that are
+// not updated load nothing and store nothing.
+template <int ST>
+__device__ __forceinline__ void local_load(const KDomain &d, const TileRec &rec, uint32_t lane, float (&f)[Q])
 {
     using S = Storage<ST>;
     constexpr uint32_t es = S::bytes;
     const auto r = make_rsrc(d.buf, d.bufbytes);
+    const uint32_t self = cell_bytes<es>(rec.tile * 64u + lane, d.tbytes);
+    if (rec.wall < 0 || lane_active(rec, lane)) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            f[k] = S::load(r, self, pop_bytes<es>(k), k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            f[k] = weight(k);
+    }
+}
+
+template <int ST, bool HIGH1>
+__device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &rec, uint32_t lane, float (&f)[Q])
+{
+    using S = Storage<ST>;
+    constexpr uint32_t es = S::bytes;
     if (rec.wall >= 0 && !lane_active(rec, lane))
         return;
+    const auto r = make_rsrc(d.buf, d.bufbytes);
     const uint32_t lin = rec.tile * 64u + lane;
     const uint32_t self = cell_bytes<es>(lin, d.tbytes);
-    float f[Q];
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-        f[k] = S::load(r, self, pop_bytes<es>(k), k);
     float ux, uy, uz;
     const float rho = collide<HIGH1>(f, d.omega, d.omega_b, d.omega_h, ux, uy, uz);
     check_state(d, rho, ux, uy, uz);
@@ -588,6 +698,14 @@ __device__ __forceinline__ void local_tile(const KDomain &d, const TileRec &rec,
                 S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, f[3 * j], 3 * j);
         }
     }
+}
+
+template <int ST, bool HIGH1>
+__device__ __forceinline__ void local_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
+{
+    float f[Q];
+    local_load<ST>(d, rec, lane, f);
+    local_finish<ST, HIGH1>(d, rec, lane, f);
 }
 
 // Inlet terms of the inlet tiles: for inlet link i of a cell, the moving-
@@ -657,17 +775,24 @@ __global__ __launch_bounds__(kBlock) void k_local_collide(KDomain d, const TileR
         local_tile<ST, HIGH1>(d, tiles[t], lane);
 }
 
-// Packed multi-domain step.  ctrl[0] = number of tile records, ctrl[1] =
-// global step.  One wave per tile record (the host keeps the grid at least
-// as large as the table); each tile belongs to one domain, whose descriptor
-// says whether, and in which phase, it takes part in this step.
-template <int ST, bool HIGH1>
-__global__ __launch_bounds__(kBlock) void k_stream_collide_batched(const KDomain *__restrict__ doms,
-                                                                const TileRec *__restrict__ tiles,
-                                                                const uint32_t *__restrict__ ctrl)
+// Packed multi-domain step, one kernel per phase.  ctrl[0] / ctrl[2] =
+// number of tile records of parity class 0 / 1, ctrl[1] = global step g.
+// The domains of class g mod 2 stream at step g and the others collide
+// locally, so each kernel walks one class's table.  One wave per tile
+// record (the host keeps the grid at least as large as the larger table);
+// each tile belongs to one domain, whose descriptor says whether it takes
+// part in this step.
+template <int ST, bool HIGH1, uint32_t PHASE>
+__global__ __launch_bounds__(kBlock) void k_collide_batched(const KDomain *__restrict__ doms,
+                                                         const TileRec *__restrict__ tiles0,
+                                                         const TileRec *__restrict__ tiles1,
+                                                         const uint32_t *__restrict__ ctrl)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t ntiles = ctrl[0], g = ctrl[1];
+    const uint32_t g = ctrl[1];
+    const uint32_t cls = (g & 1u) ^ PHASE;
+    const TileRec *tiles = cls ? tiles1 : tiles0;
+    const uint32_t ntiles = cls ? ctrl[2] : ctrl[0];
     const uint32_t nw = gridDim.x * kWavesPerBlock;
     const uint32_t w0 =
         __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
@@ -675,9 +800,9 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide_batched(const KDomain
         const TileRec rec = tiles[t];
         const KDomain &dd = doms[rec.slot];
         const uint32_t k = g - dd.step0;
-        if (k >= dd.nsteps)
+        if (k >= dd.nsteps || ((dd.ph0 + k) & 1u) != PHASE)
             continue;
-        if (((dd.ph0 + k) & 1u) == 0u)
+        if (PHASE == 0u)
             stream_tile<ST, HIGH1>(dd, rec, lane);
         else
             local_tile<ST, HIGH1>(dd, rec, lane);

@@ -301,3 +301,47 @@ def test_state_access_between_odd_and_even_steps(capi, orc, storage):
     rg, ug = d.moments()
     ro, uo = orc.moments(fl, fo)
     assert np.abs(ug - uo)[:, upd].max() <= 7 * tol * 30
+
+
+def row_aligned_channel():
+    """nx = 128 (rows of whole 64-cell tiles; y and z neighbours keep the lane
+    alignment): inlet plane, outlet plane, walls in y, z periodic, two
+    obstacles."""
+    nz, ny, nx = 6, 10, 128
+    fl = np.zeros((nz, ny, nx), np.uint8)
+    fl[:, 0, :] = I.SOLID
+    fl[:, -1, :] = I.SOLID
+    fl[:, 1:-1, 0] = I.INLET
+    fl[:, 1:-1, -1] = I.OUTLET
+    fl[1:4, 3:6, 40:44] = I.SOLID
+    fl[:, 6, 90:93] = I.SOLID
+    return fl
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_row_aligned_domain(capi, orc, storage):
+    """Random populations on a row-aligned channel: 1 and 6 steps against the
+    oracle."""
+    fl = row_aligned_channel()
+    rng = np.random.default_rng(31)
+    n_in = int((fl == I.INLET).sum())
+    uin = np.zeros((3,) + fl.shape, np.float32)
+    uin[:, fl == I.INLET] = 0.03 * rng.uniform(-1, 1, (3, n_in))
+    f0 = random_pops(orc, fl, 17)
+    rates = (1 / 0.56, 1.3, 1.0)
+    upd = updated(fl)
+    tol = 4e-7 if storage == "fp32" else 2e-3
+    for steps in (1, 6):
+        say(f"row-aligned channel {storage} steps={steps}")
+        d = capi.Domain(fl, periodic=4, storage=storage)
+        d.set_rates(*rates)
+        d.set_inlet(uin)
+        d.set_populations(f0)
+        fs = d.populations().astype(np.float64)
+        d.step(steps)
+        st, fo = orc.step(fl, fs, orc.rates_vector(*rates), steps, periodic=4, uin=uin)
+        assert st == 0
+        err = np.abs(d.populations()[:, upd] - fo[:, upd]).max()
+        say(f"  max abs err {err:.3e}")
+        assert err <= tol * steps
+        d.destroy()
