@@ -140,6 +140,54 @@ def serving_leg(full: bool, storage="fp16s"):
             "p99_ratio_serial_over_continuous": round(ser["p99_s"] / cont["p99_s"], 3)}
 
 
+def precision_leg(capi, torch, stream):
+    """Error of each storage format against the FP64 oracle reference
+    (tests/golden/precision_re6500_quarter.npz, written by the oracle): the
+    Re 6500 nozzle at a quarter of the 128 x 128 x 1536 size, 2000 steps;
+    then the full 128 x 128 x 1536 Re 6500 nozzle timed in each format."""
+    import numpy as np
+
+    from paper_2204_10566_amd import inputs as I
+
+    out = {}
+    ref_path = os.path.join(ROOT, "tests", "golden", "precision_re6500_quarter.npz")
+    if os.path.exists(ref_path):
+        ref = np.load(ref_path)
+        cfg = I.nozzle_config("re6500_quarter")
+        fl = cfg["flags"]
+        upd = ((fl == 0) | (fl == 3)).ravel()
+        ur = ref["u"].astype(np.float64)
+        rr = ref["drho"].astype(np.float64)
+        res = {"workload": "128x128x1536 Re 6500 nozzle at quarter scale (32x32x384), inlet noise 1 %, "
+                           f"{int(ref['steps'])} steps from plug flow, tau={float(ref['tau']):.7f}",
+               "reference": "tests/golden/precision_re6500_quarter.npz (FP64 oracle)"}
+        for st in ("fp32", "fp16s", "bf16s"):
+            d = capi.Domain(fl, periodic=0, storage=st, stream=stream.cuda_stream)
+            d.set_params(cfg["tau"])
+            d.set_inlet(cfg["uin"].astype(np.float32))
+            d.init_fields(None, cfg["u0"].astype(np.float32))
+            rc = d.step_status(int(ref["steps"]))
+            rho, u = d.moments()
+            d.destroy()
+            ug = u.reshape(3, -1)[:, upd].astype(np.float64)
+            dr = rho.ravel()[upd].astype(np.float64) - 1.0
+            res[st] = {"e_u": float(np.linalg.norm(ug - ur) / np.linalg.norm(ur)),
+                       "e_p": float(np.linalg.norm(dr - rr) / np.linalg.norm(rr - rr.mean())), "status": int(rc)}
+            log(f"precision {st}: {res[st]}")
+        out["quarter_scale_vs_fp64"] = res
+    cfg = I.nozzle_config("re6500")
+    for k in ("uin", "u0"):
+        cfg[k] = cfg[k].astype(np.float32)
+    speed = {"workload": "synthetic nozzle 128x128x1536, Re 6500, inlet noise 1 %, 400 steps from plug flow"}
+    for st in ("fp32", "fp16s", "bf16s"):
+        info, ms, rc, _, _ = time_steps(capi, torch, cfg, st, 400, 64, stream)
+        speed[st] = {"mlups": round(info.n_updated * 400 / (ms * 1e-3) / 1e6, 1), "status": int(rc)}
+        log(f"re6500 full size {st}: {speed[st]}")
+    speed["ratio_fp16s_vs_fp32"] = round(speed["fp16s"]["mlups"] / speed["fp32"]["mlups"], 3)
+    out["re6500_full_size"] = speed
+    return out
+
+
 def cpu_baseline(cfg, nsteps=3):
     import numpy as np
 
@@ -175,6 +223,7 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16s", "bf16s"])
     ap.add_argument("--serving", default="reduced", choices=["off", "reduced", "full"])
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path: "
@@ -261,6 +310,9 @@ def main():
                        "steps": vsteps, "status": int(vrc)}
             log(f"{st}: {v:.0f} fluid MLUPS ({v / mlups:.2f}x fp32)")
         out["variants"] = var
+    if not args.no_precision:
+        log("precision: storage formats against the FP64 reference; re6500 full-size speed")
+        out["precision"] = precision_leg(capi, torch, stream)
     if not args.no_batched:
         log("batched: 64 domains, packed vs serial")
         out["batched"] = batched_leg()

@@ -140,7 +140,7 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
         uint64_t src[Q];
         for (uint64_t t = t0; t < t1; ++t) {
             bool any = false, plain = true;
-            TileRec r{0u, (uint32_t)t, -1, 0u, kNoRec, 0u, {0u, 0u}, 0u, {0u, 0u, 0u}};
+            TileRec r{0u, (uint32_t)t, -1, 0u, kNoRec, 0u, {0u, 0u}, 0u, kMaskBB, {0u, 0u}};
             for (int l = 0; l < 64; ++l) {
                 const uint64_t c = t * 64 + l;
                 rec[l] = kNoRec;
@@ -166,6 +166,7 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
                     T.n_updated++;
                     r.act[l >> 5] |= 1u << (l & 31);
                     r.bb |= wl[l] & kMaskBB;
+                    r.bball &= wl[l];
                     r.inlm |= il[l];
                     if (outlets && !(per & 1u) && (c % nx) == (uint64_t)nx - 1)
                         r.edge = 1u;

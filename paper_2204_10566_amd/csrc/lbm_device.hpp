@@ -110,7 +110,8 @@ struct TileRec {
     uint32_t inlm;   // union of the cells' inlet links
     uint32_t act[2]; // bit l of act[l / 32]: the cell of lane l is updated
     uint32_t edge;   // 1: an updated cell of the tile lies on the outlet plane x = nx - 1
-    uint32_t pad[3];
+    uint32_t bball;  // links that every updated cell of the tile bounces back
+    uint32_t pad[2];
 };
 
 // Tile-major population layout: the 27 populations of the 64 cells of a
@@ -564,17 +565,18 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
             // The tile entry says which directions any cell of the tile
             // bounces back; for those the wave loads both candidates (for
             // the others the own load gets an offset past the end of the
-            // array, which returns 0 without a memory access), so that every
-            // load is issued before the per-cell mask arrives; the mask only
-            // selects.  Opposite directions share their weight, so one
-            // conversion serves both candidates.
+            // array, which returns 0 without a memory access; so does the
+            // neighbour load of a direction every cell bounces back), so
+            // that every load is issued before the per-cell mask arrives;
+            // the mask only selects.  Opposite directions share their
+            // weight, so one conversion serves both candidates.
             const uint32_t self = cell_bytes<es>(lin, d.tbytes);
             const bool edge_lane = EDGE && C.x == d.nx - 1u;
             m = d.wall[(uint32_t)rec.wall * 64u + lane];
             uint32_t p[Q], o[Q];
 #pragma unroll
             for (int k = 0; k < Q; ++k)
-                p[k] = S::raw(r, slot_of<es>(d, C, k, edge_lane, 0u), 0u);
+                p[k] = S::raw(r, ((rec.bball >> k) & 1u) ? d.bufbytes : slot_of<es>(d, C, k, edge_lane, 0u), 0u);
 #pragma unroll
             for (int k = 0; k < Q; ++k)
                 o[k] = S::raw(r, ((rec.bb >> k) & 1u) ? self : d.bufbytes, pop_bytes<es>(k));

@@ -221,14 +221,20 @@ def nozzle_tau(nz: Nozzle, Re: float, mach: float = 0.1) -> tuple[float, float]:
 
 
 def nozzle_config(which: str = "re500") -> dict:
-    """The two nozzle workloads: 96x96x768 at Re 500 and 128x128x1536 at
-    Re 6500 with 1 % inlet noise."""
+    """The nozzle workloads: 96x96x768 at Re 500, 128x128x1536 at Re 6500
+    with 1 % inlet noise, and that one at a quarter of its linear size."""
     if which == "re500":
         nz = Nozzle(n=96, length=768, R=24.0, r_throat=8.0)
         Re, noise = 500.0, 0.0
     elif which == "re6500":
         s = 4.0 / 3.0
         nz = Nozzle(n=128, length=1536, R=24.0 * s, r_throat=8.0 * s)
+        Re, noise = 6500.0, 0.01
+    elif which == "re6500_quarter":
+        # the 128 x 128 x 1536 Re 6500 nozzle at a quarter of its linear size
+        # (same shape, Reynolds number, Mach number and inlet noise), small
+        # enough for the FP64 oracle over a 2000-step window
+        nz = Nozzle(n=32, length=384, R=8.0, r_throat=8.0 / 3.0)
         Re, noise = 6500.0, 0.01
     else:
         raise ValueError(which)

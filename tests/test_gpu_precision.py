@@ -1,0 +1,64 @@
+"""Precision of the stored-population formats against the FP64 oracle on the
+under-resolved nozzle: the 128 x 128 x 1536 Re 6500 configuration (inlet
+noise 1 %) at a quarter of its linear size, 2000 steps from the plug-flow
+start (tau - 1/2 = 7e-5).  The reference fields are written by
+tests/golden/make_precision_reference.py (oracle only).
+
+Errors: e_u = |u - u_ref|_2 / |u_ref|_2 and e_p = |rho - rho_ref|_2 /
+|rho_ref - mean(rho_ref)|_2 over the updated cells (pressure p = rho / 3).
+FP32 storage rounds each stored population to 2^-24 relative, FP16-shifted
+storage to 2^-11 of (f - w) 2^14, i.e. about 3e-5 absolute on f; the bound
+for FP16 is the 1e-3 velocity error the method is held to; BF16 (8
+significand bits) is reported with a looser bound."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2204_10566_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "precision_re6500_quarter.npz")
+BOUND_U = {"fp32": 1e-4, "fp16s": 1e-3, "bf16s": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2204_10566_amd import capi
+
+    return capi
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def precision_errors(capi, storage):
+    ref = np.load(REF)
+    cfg = I.nozzle_config("re6500_quarter")
+    fl = cfg["flags"]
+    d = capi.Domain(fl, periodic=0, storage=storage)
+    d.set_params(cfg["tau"])
+    d.set_inlet(cfg["uin"].astype(np.float32))
+    d.init_fields(None, cfg["u0"].astype(np.float32))
+    st = d.step_status(int(ref["steps"]))
+    rho, u = d.moments()
+    d.destroy()
+    upd = ((fl == I.FLUID) | (fl == I.OUTLET)).ravel()
+    ug = u.reshape(3, -1)[:, upd].astype(np.float64)
+    dr = rho.ravel()[upd].astype(np.float64) - 1.0
+    ur = ref["u"].astype(np.float64)
+    rr = ref["drho"].astype(np.float64)
+    e_u = float(np.linalg.norm(ug - ur) / np.linalg.norm(ur))
+    e_p = float(np.linalg.norm(dr - rr) / np.linalg.norm(rr - rr.mean()))
+    return st, e_u, e_p
+
+
+@pytest.mark.skipif(not os.path.exists(REF), reason="reference not generated")
+@pytest.mark.parametrize("storage", ["fp32", "fp16s", "bf16s"])
+def test_precision_against_fp64(capi, storage):
+    st, e_u, e_p = precision_errors(capi, storage)
+    say(f"re6500 quarter, 2000 steps, {storage}: e_u={e_u:.3e} e_p={e_p:.3e}")
+    assert st == 0
+    assert e_u <= BOUND_U[storage]
