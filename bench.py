@@ -188,6 +188,43 @@ def precision_leg(capi, torch, stream):
     return out
 
 
+def stability_leg(capi, stream):
+    """Stability envelope at tau -> 1/2: a 64^3 periodic double shear layer
+    (u0 = 0.1, FP32) run 2000 steps at decreasing tau - 1/2 for several
+    settings of the higher-order rates; reports the smallest tau - 1/2 that
+    stays stable for each setting."""
+    import numpy as np
+
+    from paper_2204_10566_amd import inputs as I
+
+    n = 64
+    fl = I.periodic_box(n)
+    u0 = I.double_shear_layer_velocity(n, 0.1).astype(np.float32)
+    eps = [1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5]
+    settings = {"omega_3..6 = 1 (paper)": (1.0, 1.0, 1.0, 1.0),
+                "omega_3..6 = 1.2": (1.2, 1.2, 1.2, 1.2),
+                "omega_3..6 = 1.6": (1.6, 1.6, 1.6, 1.6),
+                "omega_3 = omega (shear), rest 1": None}
+    out = {"workload": "64^3 periodic double shear layer, u0 = 0.1, kappa 80, FP32, 2000 steps per point",
+           "tau_minus_half_tried": eps}
+    for name, rates in settings.items():
+        smallest = None
+        for e in eps:
+            tau = 0.5 + e
+            d = capi.Domain(fl, periodic=7, storage="fp32", stream=stream.cuda_stream)
+            d.set_rates(1.0 / tau, 1.0 / tau, 1.0)
+            d.set_order_rates(*(rates if rates is not None else (1.0 / tau, 1.0, 1.0, 1.0)))
+            d.init_fields(None, u0)
+            rc = d.step_status(2000)
+            d.destroy()
+            if rc != capi.OK:
+                break
+            smallest = e
+        out[name] = smallest
+        log(f"stability {name}: smallest stable tau - 1/2 = {smallest}")
+    return out
+
+
 def cpu_baseline(cfg, nsteps=3):
     import numpy as np
 
@@ -224,6 +261,7 @@ def main():
     ap.add_argument("--serving", default="reduced", choices=["off", "reduced", "full"])
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-stability", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path: "
@@ -313,6 +351,9 @@ def main():
     if not args.no_precision:
         log("precision: storage formats against the FP64 reference; re6500 full-size speed")
         out["precision"] = precision_leg(capi, torch, stream)
+    if not args.no_stability:
+        log("stability envelope (double shear layer)")
+        out["stability"] = stability_leg(capi, stream)
     if not args.no_batched:
         log("batched: 64 domains, packed vs serial")
         out["batched"] = batched_leg()

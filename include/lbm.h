@@ -151,6 +151,16 @@ int lbm_set_params(lbm_domain *d, double tau, double omega_bulk, double omega_hi
 int lbm_set_rates(lbm_domain *d, double omega, double omega_bulk, double omega_high);
 
 /*
+ * One relaxation rate per order of the higher central moments (the paper
+ * sets them all to one, Sec. 2.1 after Eq. (8); App. A after Eq. (A.6)).
+ * The central moment H_{x^a y^b z^c}, a, b, c <= 2, has order a + b + c;
+ * omega3..omega6 relax the orders 3..6, each in [0, 2].  lbm_set_params and
+ * lbm_set_rates set all four to omega_high.  Errors: LBM_ERR_ARG when out
+ * of range, LBM_ERR_STATE for a domain resident in a batch.
+ */
+int lbm_set_order_rates(lbm_domain *d, double omega3, double omega4, double omega5, double omega6);
+
+/*
  * Inlet velocity (Sec. 2.2, Eq. (12) profile, or any field).
  *   u_in  host, 3*ncells floats, layout [component][cell]; read only at
  *         LBM_INLET cells.  A link from an inlet cell s into a fluid cell x
@@ -205,6 +215,33 @@ int lbm_get_populations(lbm_domain *d, float *f);
 /* Overwrite the stored populations (FP32 values of f_i, [i][cell], host);
  * converted to the domain's storage. */
 int lbm_set_populations(lbm_domain *d, const float *f);
+
+/*
+ * Time statistics (Sec. 2.2, Eqs. (15)-(18): mean velocity and Reynolds
+ * stresses; Eq. (19): viscous shear stress, with the strain rate from the
+ * second-order Hermite coefficients, App. A, Eqs. (A.7)-(A.8)).  While on,
+ * every local-phase step (every second step) adds, for each updated cell,
+ * u, u_a u_b and sigma_ab = 2 rho nu S_ab = -(1 - omega/2) M_ab of the
+ * pre-collision state it collides (M_ab: central second-order Hermite
+ * moment, omega the shear rate), summed in FP32 on the device
+ * (15 * 64 * n_tiles floats).  Also accumulates while the domain is in a
+ * batch.
+ * lbm_stats_enable(d, 1) clears the sums and starts; (d, 0) stops and keeps
+ * them.
+ */
+int lbm_stats_enable(lbm_domain *d, int on);
+
+/*
+ * Means of the statistics since the last lbm_stats_enable(d, 1).
+ *   mean_u      host, 3*ncells floats [component][cell]
+ *   mean_uu     host, 6*ncells floats: <u_x u_x>, <u_y u_y>, <u_z u_z>,
+ *               <u_x u_y>, <u_x u_z>, <u_y u_z> (Reynolds stress =
+ *               <u_a u_b> - <u_a><u_b>)
+ *   mean_sigma  host, 6*ncells floats, same component order
+ *   samples     number of samples in the means
+ * Cells that are not updated read 0; all outputs are 0 without samples.
+ */
+int lbm_stats_get(lbm_domain *d, float *mean_u, float *mean_uu, float *mean_sigma, uint64_t *samples);
 
 int lbm_domain_get_info(const lbm_domain *d, lbm_domain_info *info);
 

@@ -69,6 +69,7 @@ def lib():
                                   ctypes.c_int, dp, dp]
         L.oracle_step.restype = ctypes.c_int
         L.oracle_moments.argtypes = [u8p, ctypes.c_long, dp, dp, dp]
+        L.oracle_stress.argtypes = [u8p, ctypes.c_long, dp, ctypes.c_double, dp]
         L.oracle_run_cells.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, dp, dp, dp,
                                        dp, ctypes.c_int, ctypes.c_long, lp, dp]
         L.oracle_run_cells.restype = ctypes.c_int
@@ -203,6 +204,17 @@ def moments(flags, f):
     u = np.zeros((3,) + fl.shape)
     lib().oracle_moments(flp, fl.size, _dp(fa), _dp(rho), _dp(u))
     return rho, u
+
+
+def stress(flags, f, omega):
+    """Viscous stress sigma[6, nz, ny, nx] (xx, yy, zz, xy, xz, yz) of a
+    pre-collision state (Sec. 2.2, Eq. (19); App. A, Eqs. (A.7)-(A.8)):
+    sigma = -(1 - omega/2) times the central second-order Hermite moment."""
+    fl, flp = _u8(flags)
+    fa = _f64(f)
+    sig = np.zeros((6,) + fl.shape)
+    lib().oracle_stress(flp, fl.size, _dp(fa), float(omega), _dp(sig))
+    return sig
 
 
 def run_cells(flags, cells, rates, nsteps, periodic=0, uin=None, rho0=None, u0=None):

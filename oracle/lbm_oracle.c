@@ -519,6 +519,42 @@ void oracle_moments(const uint8_t *flags, long ncells, const double *f, double *
     }
 }
 
+/* Viscous stress of a pre-collision state (Sec. 2.2, Eq. (19), with the
+ * strain rate from the second-order Hermite coefficients, App. A,
+ * Eqs. (A.7)-(A.8)).  Reading of the garbled sign and factor: the
+ * non-equilibrium second-order central Hermite moment
+ *     M_ab = sum_i f_i [(c_ia - u_a)(c_ib - u_b) - theta0 delta_ab]
+ * (f^eq contributes nothing to it) equals -2 rho theta0 tau S_ab to
+ * leading order, so sigma_ab = 2 rho nu S_ab = -(1 - omega/2) M_ab with
+ * nu = theta0 (tau - 1/2), omega = 1/tau.  Out: sigma[6][ncells] in the
+ * order xx, yy, zz, xy, xz, yz; zero at cells that are not updated. */
+void oracle_stress(const uint8_t *flags, long ncells, const double *f, double omega, double *sigma)
+{
+    static const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+    oracle_init_tables();
+#pragma omp parallel for schedule(static)
+    for (long cell = 0; cell < ncells; ++cell) {
+        double out[6] = {0, 0, 0, 0, 0, 0};
+        if (updatable(flags[cell])) {
+            double fc[NQ], r = 0.0, u[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < NQ; ++i)
+                fc[i] = f[(long)i * ncells + cell];
+            oracle_cell_moments(fc, &r, u);
+            for (int k = 0; k < 6; ++k) {
+                const int a = pa[k], b = pb[k];
+                double m = 0.0;
+                for (int i = 0; i < NQ; ++i) {
+                    const double xa = g_c[i][a] - u[a], xb = g_c[i][b] - u[b];
+                    m += fc[i] * (xa * xb - (a == b ? THETA0 : 0.0));
+                }
+                out[k] = -(1.0 - 0.5 * omega) * m;
+            }
+        }
+        for (int k = 0; k < 6; ++k)
+            sigma[(long)k * ncells + cell] = out[k];
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* Sampled run: the post-collision populations after nsteps at a few  */
 /* listed cells of a large domain, starting from f^eq(rho0, u0).  Only */

@@ -52,6 +52,7 @@ SIGNATURES = {
                                              ctypes.c_int, _vp, _vp, ctypes.POINTER(_vp)]),
     "lbm_set_params": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_rates": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "lbm_set_order_rates": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_inlet": (ctypes.c_int, [_vp, _fp]),
     "lbm_set_inlet_cells": (ctypes.c_int, [_vp, _fp]),
     "lbm_init_fields": (ctypes.c_int, [_vp, _fp, _fp]),
@@ -61,6 +62,8 @@ SIGNATURES = {
     "lbm_get_populations": (ctypes.c_int, [_vp, _fp]),
     "lbm_set_populations": (ctypes.c_int, [_vp, _fp]),
     "lbm_domain_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(DomainInfo)]),
+    "lbm_stats_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lbm_stats_get": (ctypes.c_int, [_vp, _fp, _fp, _fp, ctypes.POINTER(ctypes.c_uint64)]),
     "lbm_destroy": (ctypes.c_int, [_vp]),
     "lbm_last_error": (ctypes.c_char_p, []),
     "lbm_batch_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
@@ -148,6 +151,9 @@ class Domain:
     def set_rates(self, omega, omega_bulk, omega_high):
         check(lbm_set_rates(self.h, omega, omega_bulk, omega_high))
 
+    def set_order_rates(self, omega3, omega4, omega5, omega6):
+        check(lbm_set_order_rates(self.h, omega3, omega4, omega5, omega6))
+
     def set_inlet(self, uin):
         a, p = _f32(uin, 3 * self.ncells)
         check(lbm_set_inlet(self.h, p))
@@ -185,6 +191,19 @@ class Domain:
     def set_populations(self, f):
         a, p = _f32(f, Q * self.ncells)
         check(lbm_set_populations(self.h, p))
+
+    def stats_enable(self, on=True):
+        check(lbm_stats_enable(self.h, 1 if on else 0))
+
+    def stats(self):
+        """(mean u [3,...], mean u_a u_b [6,...], mean sigma [6,...], samples)."""
+        mu = np.empty((3,) + self.shape, np.float32)
+        muu = np.empty((6,) + self.shape, np.float32)
+        ms = np.empty((6,) + self.shape, np.float32)
+        n = ctypes.c_uint64()
+        check(lbm_stats_get(self.h, mu.ctypes.data_as(_fp), muu.ctypes.data_as(_fp), ms.ctypes.data_as(_fp),
+                            ctypes.byref(n)))
+        return mu, muu, ms, int(n.value)
 
     def destroy(self):
         if self.h:

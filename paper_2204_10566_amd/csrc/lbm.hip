@@ -140,7 +140,7 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
         uint64_t src[Q];
         for (uint64_t t = t0; t < t1; ++t) {
             bool any = false, plain = true;
-            TileRec r{0u, (uint32_t)t, -1, 0u, kNoRec, 0u, {0u, 0u}, 0u, kMaskBB, {0u, 0u}};
+            TileRec r{0u, (uint32_t)t, -1, 0u, kNoRec, 0u, {0u, 0u}, 0u, kMaskBB, 0u, 0u};
             for (int l = 0; l < 64; ++l) {
                 const uint64_t c = t * 64 + l;
                 rec[l] = kNoRec;
@@ -200,6 +200,7 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
                 r.wall += off;
             if (r.inl != kNoRec)
                 r.inl += out.n_inl;
+            r.ord = (uint32_t)out.recs.size();
             out.recs.push_back(r);
         }
         out.n_inl += part[p].n_inl;
@@ -238,6 +239,9 @@ struct lbm_domain {
     uint64_t bytes = 0;   // its size
     int phase = 0;        // phase of the stored state (k_stream_collide)
     bool outlets = false; // the domain has outlet cells
+    float *d_stats = nullptr;   // statistics sums, [15][64 ntiles]
+    bool stats_on = false;
+    uint64_t stats_samples = 0; // local steps accumulated
     uint8_t *d_flags = nullptr;
     TileRec *d_tiles = nullptr;
     uint32_t *d_wall = nullptr, *d_inlet = nullptr, *d_inlrec = nullptr;
@@ -247,7 +251,9 @@ struct lbm_domain {
     std::vector<uint64_t> inlet_cells;     // inlet cells, ascending (index = inlet ordinal)
     uint32_t *d_status = nullptr;
     uint64_t ntiles = 0, nwall = 0, n_updated = 0;
-    double omega = 1.0, omega_b = 1.0, omega_h = 1.0;
+    double omega = 1.0, omega_b = 1.0;
+    double omega_o[4] = {1.0, 1.0, 1.0, 1.0}; // orders 3..6
+    bool high1() const { return omega_o[0] == 1.0 && omega_o[1] == 1.0 && omega_o[2] == 1.0 && omega_o[3] == 1.0; }
     bool unstable = false;
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
@@ -316,6 +322,8 @@ KDomain kdomain(const lbm_domain *d)
     KDomain k{};
     k.buf = d->buf;
     k.flags = d->d_flags;
+    k.stats = d->stats_on ? d->d_stats : nullptr;
+    k.sstride = (uint32_t)(d->ntiles * 64);
     k.wall = d->d_wall;
     k.iterm = d->d_iterm;
     k.status = d->d_status;
@@ -332,7 +340,8 @@ KDomain kdomain(const lbm_domain *d)
     k.periodic = d->periodic;
     k.omega = (float)d->omega;
     k.omega_b = (float)d->omega_b;
-    k.omega_h = (float)d->omega_h;
+    for (int n = 0; n < 4; ++n)
+        k.omega_o[n] = (float)d->omega_o[n];
     return k;
 }
 
@@ -364,7 +373,7 @@ hipError_t launch_step(const lbm_domain *d, uint32_t phase)
 {
     if (d->ntiles == 0)
         return hipSuccess;
-    const bool h1 = d->omega_h == 1.0;
+    const bool h1 = d->high1();
     switch (d->storage) {
     case LBM_FP32:
         return h1 ? launch_step_t<ST_FP32, true>(d, phase) : launch_step_t<ST_FP32, false>(d, phase);
@@ -427,6 +436,7 @@ void free_domain(lbm_domain *d)
         dfree(s, d->d_inlrec);
         dfree(s, d->d_uin);
         dfree(s, d->d_iterm);
+        dfree(s, d->d_stats);
         dfree(s, d->d_status);
         if (d->own_stream)
             (void)hipStreamDestroy(s);
@@ -598,7 +608,6 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     if (build_inlet_terms(d) != hipSuccess)
         return bail(fail(LBM_ERR_DEVICE, "inlet terms"));
     d->omega = d->omega_b = 1.0 / 0.6;
-    d->omega_h = 1.0;
     int rc = init_eq(d, nullptr, nullptr);
     if (rc == LBM_OK && hipStreamSynchronize(d->stream) != hipSuccess)
         rc = fail(LBM_ERR_DEVICE, "initialisation failed");
@@ -653,7 +662,7 @@ int build_graph(lbm_domain *d)
     uint32_t nt = (uint32_t)d->ntiles;
     hipGraphNode_t prev = nullptr;
     for (int s = 0; s < kGraphSteps; ++s) {
-        const void *fn = step_kernel(d->storage, d->omega_h == 1.0, (uint32_t)(s & 1));
+        const void *fn = step_kernel(d->storage, d->high1(), (uint32_t)(s & 1));
         void *args[] = {&k, &tiles, &nt};
         hipGraphNode_t node = nullptr;
         hipError_t e = add_kernel_node(g, prev, fn, step_grid(d, (uint32_t)(s & 1)), kBlock, args, &node);
@@ -713,7 +722,24 @@ int lbm_set_rates(lbm_domain *d, double omega, double omega_bulk, double omega_h
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     d->omega = omega;
     d->omega_b = omega_bulk;
-    d->omega_h = omega_high;
+    for (int n = 0; n < 4; ++n)
+        d->omega_o[n] = omega_high;
+    d->graph_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_set_order_rates(lbm_domain *d, double omega3, double omega4, double omega5, double omega6)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    const double w[4] = {omega3, omega4, omega5, omega6};
+    for (double v : w)
+        if (!(v >= 0 && v <= 2))
+            return fail(LBM_ERR_ARG, "rates must lie in [0, 2]");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    for (int n = 0; n < 4; ++n)
+        d->omega_o[n] = w[n];
     d->graph_dirty = true;
     return LBM_OK;
 }
@@ -810,10 +836,12 @@ int lbm_step(lbm_domain *d, int n)
     if (d->ntiles == 0) // nothing is updated, the state stays as it is
         return LBM_OK;
     int left = n;
+    uint64_t local_steps = 0;
     if (left > 0 && d->phase == 1) {
         HIP_TRY(launch_step(d, 1));
         d->phase = 0;
         --left;
+        ++local_steps;
     }
     if (left >= kGraphSteps) {
         if (d->graph_dirty)
@@ -822,13 +850,17 @@ int lbm_step(lbm_domain *d, int n)
         while (left >= kGraphSteps) {
             HIP_TRY(hipGraphLaunch(d->graph, d->stream));
             left -= kGraphSteps;
+            local_steps += kGraphSteps / 2;
         }
     }
     while (left > 0) {
         HIP_TRY(launch_step(d, (uint32_t)d->phase));
+        local_steps += (uint64_t)d->phase;
         d->phase ^= 1;
         --left;
     }
+    if (d->stats_on)
+        d->stats_samples += local_steps;
     if (int rc = sync_status(d))
         return rc;
     if (d->unstable)
@@ -925,6 +957,63 @@ int lbm_set_populations(lbm_domain *d, const float *f)
             rc = fail(LBM_ERR_DEVICE, "population import failed");
     }
     dfree(d->stream, df);
+    return rc;
+}
+
+int lbm_stats_enable(lbm_domain *d, int on)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    if (on) {
+        const size_t bytes = (size_t)15 * d->ntiles * 64 * sizeof(float);
+        if (!d->d_stats && bytes) {
+            if (dalloc(d->stream, (void **)&d->d_stats, bytes) != hipSuccess)
+                return fail(LBM_ERR_OOM, "statistics sums (%zu bytes)", bytes);
+            d->device_bytes += bytes;
+        }
+        if (bytes)
+            HIP_TRY(hipMemsetAsync(d->d_stats, 0, bytes, d->stream));
+        HIP_TRY(hipStreamSynchronize(d->stream));
+        d->stats_samples = 0;
+    }
+    d->stats_on = on != 0;
+    d->graph_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_stats_get(lbm_domain *d, float *mean_u, float *mean_uu, float *mean_sigma, uint64_t *samples)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!mean_u || !mean_uu || !mean_sigma || !samples)
+        return fail(LBM_ERR_ARG, "null output");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    *samples = d->stats_samples;
+    const size_t n = d->ncells;
+    float *dout = nullptr;
+    if (dalloc(d->stream, (void **)&dout, 15 * n * sizeof(float)) != hipSuccess)
+        return fail(LBM_ERR_OOM, "staging buffer");
+    int rc = LBM_OK;
+    if (hipMemsetAsync(dout, 0, 15 * n * sizeof(float), d->stream) != hipSuccess)
+        rc = fail(LBM_ERR_DEVICE, "staging clear failed");
+    if (rc == LBM_OK && d->d_stats && d->stats_samples && d->ntiles) {
+        KDomain k = kdomain(d);
+        k.stats = d->d_stats;
+        const uint32_t blocks = (uint32_t)((d->ntiles + 3) / 4);
+        hipLaunchKernelGGL(k_stats_export, dim3(blocks), dim3(256), 0, d->stream, k, (const TileRec *)d->d_tiles,
+                           (uint32_t)d->ntiles, (float)(1.0 / (double)d->stats_samples), dout);
+        if (hipGetLastError() != hipSuccess)
+            rc = fail(LBM_ERR_DEVICE, "statistics export failed");
+    }
+    if (rc == LBM_OK &&
+        (copy_sync(d->stream, mean_u, dout, 3 * n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+         copy_sync(d->stream, mean_uu, dout + 3 * n, 6 * n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+         copy_sync(d->stream, mean_sigma, dout + 9 * n, 6 * n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess))
+        rc = fail(LBM_ERR_DEVICE, "statistics download failed");
+    dfree(d->stream, dout);
     return rc;
 }
 

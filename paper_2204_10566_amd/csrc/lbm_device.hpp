@@ -92,7 +92,10 @@ struct KDomain {
     uint32_t nx, ny, nz, ncells;
     FastDiv dnx, dny;
     uint32_t periodic;
-    float omega, omega_b, omega_h;
+    float omega, omega_b;
+    float omega_o[4];        // rates of the central moments of order 3, 4, 5, 6
+    float *stats;            // statistics sums [15][sstride] (see local_finish), or null
+    uint32_t sstride;        // 64 x number of tiles
     // batched execution: the domain takes part in global steps
     // [step0, step0 + nsteps), starting in phase ph0.
     uint32_t step0, nsteps, ph0, pad;
@@ -111,7 +114,8 @@ struct TileRec {
     uint32_t act[2]; // bit l of act[l / 32]: the cell of lane l is updated
     uint32_t edge;   // 1: an updated cell of the tile lies on the outlet plane x = nx - 1
     uint32_t bball;  // links that every updated cell of the tile bounces back
-    uint32_t pad[2];
+    uint32_t ord;    // position of the tile in its domain's tile list
+    uint32_t pad;
 };
 
 // Tile-major population layout: the 27 populations of the 64 cells of a
@@ -235,7 +239,7 @@ template <> struct Storage<ST_BF16S> {
 // zero by definition of u.  The inverse is the same three sweeps as below,
 // over the ten moments that are left.
 __device__ __forceinline__ float collide_h1(float (&f)[Q], float omega, float omega_b, float &ux, float &uy,
-                                            float &uz)
+                                            float &uz, float (&m2)[6])
 {
     // per (c_y, c_z) row t = b + 3c: s0 = sum over c_x, s1 = first, s2 = second moment in x
     float s0[9], s1[9], s2[9];
@@ -279,9 +283,15 @@ __device__ __forceinline__ float collide_h1(float (&f)[Q], float omega, float om
     float mxx = __builtin_fmaf(-jx, ux, sxx) - tr0;
     float myy = __builtin_fmaf(-jy, uy, syy) - tr0;
     float mzz = __builtin_fmaf(-jz, uz, szz) - tr0;
-    const float mxy = ks * __builtin_fmaf(-jx, uy, sxy);
-    const float mxz = ks * __builtin_fmaf(-jx, uz, sxz);
-    const float myz = ks * __builtin_fmaf(-jy, uz, syz);
+    m2[0] = mxx;
+    m2[1] = myy;
+    m2[2] = mzz;
+    m2[3] = __builtin_fmaf(-jx, uy, sxy);
+    m2[4] = __builtin_fmaf(-jx, uz, sxz);
+    m2[5] = __builtin_fmaf(-jy, uz, syz);
+    const float mxy = ks * m2[3];
+    const float mxz = ks * m2[4];
+    const float myz = ks * m2[5];
     {
         const float d = (kb - ks) * ((mxx + myy + mzz) * (1.0f / 3.0f));
         mxx = __builtin_fmaf(ks, mxx, d);
@@ -301,11 +311,12 @@ __device__ __forceinline__ float collide_h1(float (&f)[Q], float omega, float om
     return rho;
 }
 
-// Forward central-Hermite transform and relaxation for a general omega_high:
+// Forward central-Hermite transform and relaxation for general rates of the
+// orders 3..6 (the order of moment slot a + 3b + 9c is a + b + c):
 // three sweeps of the 1-D map (x raw, then shifted to the central moments
 // about ux; y and z directly central), then the relaxation.
-__device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float omega_b, float omega_h, float &ux,
-                                               float &uy, float &uz)
+__device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float omega_b, const float (&omega_o)[4],
+                                               float &ux, float &uy, float &uz, float (&m2)[6])
 {
     // x sweep, raw: s0 = sum, s1 = first moment, s2 = second moment
 #pragma unroll
@@ -362,8 +373,14 @@ __device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float
 
     // relaxation (Sec. 2.1 after Eq. (8); App. A after Eq. (A.6)):
     // order 0 and 1 conserved; second order: deviator and off-diagonal at
-    // omega, trace at omega_b; order >= 3 at omega_h.
-    const float ks = 1.f - omega, kb = 1.f - omega_b, kh = 1.f - omega_h;
+    // omega, trace at omega_b; order n >= 3 at omega_o[n - 3].
+    m2[0] = f[2];
+    m2[1] = f[6];
+    m2[2] = f[18];
+    m2[3] = f[4];
+    m2[4] = f[10];
+    m2[5] = f[12];
+    const float ks = 1.f - omega, kb = 1.f - omega_b;
     f[4] *= ks;
     f[10] *= ks;
     f[12] *= ks;
@@ -374,19 +391,21 @@ __device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float
         f[6] = __builtin_fmaf(ks, f[6], d);
         f[18] = __builtin_fmaf(ks, f[18], d);
     }
-    constexpr int high[17] = {5, 7, 8, 11, 13, 14, 15, 16, 17, 19, 20, 21, 22, 23, 24, 25, 26};
 #pragma unroll
-    for (int k = 0; k < 17; ++k)
-        f[high[k]] *= kh;
+    for (int k = 0; k < Q; ++k) {
+        const int n = k % 3 + (k / 3) % 3 + k / 9;
+        if (n >= 3)
+            f[k] *= 1.f - omega_o[n - 3];
+    }
     return rho;
 }
 
 template <bool HIGH1>
-__device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega_b, float omega_h, float &ux,
-                                         float &uy, float &uz)
+__device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega_b, const float (&omega_o)[4],
+                                         float &ux, float &uy, float &uz, float (&m2)[6])
 {
-    const float rho = HIGH1 ? collide_h1(f, omega, omega_b, ux, uy, uz)
-                            : moments_relax(f, omega, omega_b, omega_h, ux, uy, uz);
+    const float rho = HIGH1 ? collide_h1(f, omega, omega_b, ux, uy, uz, m2)
+                            : moments_relax(f, omega, omega_b, omega_o, ux, uy, uz, m2);
     // inverse sweeps z, y, x: raw moments R0 = m0, R1 = m1 + u m0,
     // R2 = m2 + 2 u m1 + (u^2 + theta0) m0; then f(+1) = (R2 + R1)/2,
     // f(-1) = (R2 - R1)/2, f(0) = R0 - R2.
@@ -591,8 +610,8 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
         }
     }
 
-    float ux, uy, uz;
-    const float rho = collide<HIGH1>(f, d.omega, d.omega_b, d.omega_h, ux, uy, uz);
+    float ux, uy, uz, m2[6];
+    const float rho = collide<HIGH1>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
 
     // The slot addresses are recomputed rather than kept through the
@@ -674,6 +693,12 @@ __device__ __forceinline__ void local_load(const KDomain &d, const TileRec &rec,
     }
 }
 
+// With statistics on (d.stats), the local step adds per cell, from the
+// pre-collision state it collides: u (3 sums), u_a u_b (6: xx yy zz xy xz yz)
+// and the viscous stress sigma_ab = 2 rho nu S_ab = -(1 - omega/2) M_ab from
+// the central second-order Hermite moments M_ab (Sec. 2.2, Eqs. (15)-(19);
+// App. A, Eqs. (A.7)-(A.8)); sums of component c at stats[c * sstride +
+// 64 ord + lane].
 template <int ST, bool HIGH1>
 __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &rec, uint32_t lane, float (&f)[Q])
 {
@@ -684,12 +709,21 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
     const auto r = make_rsrc(d.buf, d.bufbytes);
     const uint32_t lin = rec.tile * 64u + lane;
     const uint32_t self = cell_bytes<es>(lin, d.tbytes);
-    float ux, uy, uz;
-    const float rho = collide<HIGH1>(f, d.omega, d.omega_b, d.omega_h, ux, uy, uz);
+    float ux, uy, uz, m2[6];
+    const float rho = collide<HIGH1>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
 #pragma unroll
     for (int k = 0; k < Q; ++k)
         S::store(r, self, pop_bytes<es>(Q - 1 - k), f[k], k);
+    if (d.stats) {
+        float *acc = d.stats + rec.ord * 64u + lane;
+        const float ks = -(1.f - 0.5f * d.omega);
+        const float v[15] = {ux, uy, uz, ux * ux, uy * uy, uz * uz, ux * uy, ux * uz, uy * uz,
+                             ks * m2[0], ks * m2[1], ks * m2[2], ks * m2[3], ks * m2[4], ks * m2[5]};
+#pragma unroll
+        for (int c = 0; c < 15; ++c)
+            acc[(size_t)c * d.sstride] += v[c];
+    }
     if (rec.edge) {
         const uint32_t q = fdiv(lin, d.dnx);
         if (lin - q * d.nx == d.nx - 1u) {
@@ -954,6 +988,26 @@ __global__ __launch_bounds__(256) void k_moments(KDomain d, float *__restrict__ 
     u[c] = jx;
     u[d.ncells + c] = jy;
     u[2u * d.ncells + c] = jz;
+}
+
+// Means of the statistics sums (scale = 1 / samples) to [component][cell]
+// arrays (3 for u, 6 for u_a u_b, 6 for sigma); cells that are not updated
+// are left as they are (the host zeroes the outputs).  One wave per tile.
+__global__ __launch_bounds__(256) void k_stats_export(KDomain d, const TileRec *__restrict__ tiles, uint32_t ntiles,
+                                                      float scale, float *__restrict__ out)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
+    if (t >= ntiles)
+        return;
+    const TileRec rec = tiles[t];
+    if (!lane_active(rec, lane) && rec.wall >= 0)
+        return;
+    const uint32_t cell = rec.tile * 64u + lane;
+    if (cell >= d.ncells)
+        return;
+    for (int c = 0; c < 15; ++c)
+        out[(size_t)c * d.ncells + cell] = d.stats[(size_t)c * d.sstride + rec.ord * 64u + lane] * scale;
 }
 
 // Phase-0 state <-> FP32 values of f_i, layout [i][cell] without padding.

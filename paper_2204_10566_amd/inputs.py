@@ -55,6 +55,19 @@ def taylor_green_velocity(nx: int, ny: int, nz: int, u0: float) -> np.ndarray:
     return u
 
 
+def double_shear_layer_velocity(n: int, u0: float, kappa: float = 80.0, delta: float = 0.05) -> np.ndarray:
+    """Periodic double shear layer on an n x n x n box (a standard stability
+    stress case): u_x = u0 tanh(kappa (y' - 1/4)) for y' <= 1/2 and
+    u0 tanh(kappa (3/4 - y')) above, u_y = delta u0 sin(2 pi (x' + 1/4)),
+    u_z = 0, with x' = x / n, y' = y / n at integer cell coordinates."""
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    yp, xp = y / n, x / n
+    u = np.zeros((3, n, n, n))
+    u[0] = np.where(yp <= 0.5, u0 * np.tanh(kappa * (yp - 0.25)), u0 * np.tanh(kappa * (0.75 - yp)))
+    u[1] = delta * u0 * np.sin(2 * math.pi * (xp + 0.25))
+    return u
+
+
 def taylor_green_2d_velocity(nx: int, ny: int, u0: float) -> np.ndarray:
     """z-independent Taylor-Green vortex on an nx x ny x 1 box."""
     kx, ky = 2 * math.pi / nx, 2 * math.pi / ny

@@ -345,3 +345,30 @@ def test_row_aligned_domain(capi, orc, storage):
         say(f"  max abs err {err:.3e}")
         assert err <= tol * steps
         d.destroy()
+
+
+@pytest.mark.parametrize("order_rates", [(1.3, 0.8, 1.6, 0.5), (1.0, 1.0, 1.0, 1.2)])
+def test_per_order_rates(capi, orc, order_rates):
+    """A separate rate for each order 3..6 of the higher central moments:
+    one and four steps from random populations on the geometry with every
+    boundary kind."""
+    fl = mixed_geometry()
+    rng = np.random.default_rng(41)
+    uin = np.zeros((3,) + fl.shape, np.float32)
+    uin[:, fl == I.INLET] = 0.02 * rng.uniform(-1, 1, (3, int((fl == I.INLET).sum())))
+    f0 = random_pops(orc, fl, 43)
+    upd = updated(fl)
+    for steps in (1, 4):
+        say(f"order rates {order_rates} steps={steps}")
+        d = capi.Domain(fl, periodic=4)
+        d.set_rates(1 / 0.58, 1.1, 1.0)
+        d.set_order_rates(*order_rates)
+        d.set_inlet(uin)
+        d.set_populations(f0)
+        d.step(steps)
+        st, fo = orc.step(fl, f0, orc.rates_vector(1 / 0.58, 1.1, order_rates=order_rates), steps, periodic=4, uin=uin)
+        assert st == 0
+        err = np.abs(d.populations()[:, upd] - fo[:, upd]).max()
+        say(f"  max abs err {err:.3e}")
+        assert err <= 4e-7 * steps
+        d.destroy()

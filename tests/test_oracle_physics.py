@@ -225,3 +225,39 @@ def test_run_cells_matches_full_step(orc):
     st, fc = orc.run_cells(fl, cells, rates, 3, periodic=0, uin=cfg["uin"], u0=cfg["u0"])
     assert st == 0
     assert np.array_equal(fc, f.reshape(27, -1)[:, cells])
+
+
+def test_stress_of_equilibrium_is_zero(orc):
+    """The central second-order Hermite moments of f^eq vanish, so an
+    equilibrium state carries no viscous stress (Sec. 2.2, Eq. (19))."""
+    fl = np.zeros((3, 4, 5), np.uint8)
+    rng = np.random.default_rng(2)
+    rho = 1 + 0.05 * rng.uniform(-1, 1, fl.shape)
+    u = 0.1 * rng.uniform(-1, 1, (3,) + fl.shape)
+    f = orc.init_fields(fl, rho, u)
+    assert np.abs(orc.stress(fl, f, 1 / 0.7)).max() < 1e-14
+
+
+def test_stress_of_shear_wave_is_newtonian(orc):
+    """A decaying shear wave u_x = A sin(k y): the stress read from the
+    second-order moments equals rho nu du_x/dy = rho nu A k cos(k y) with
+    nu = theta0 (tau - 1/2) (Eq. (19)), to within the O(k^2) error, and the
+    other components vanish."""
+    n, tau, u0 = 64, 0.8, 0.02
+    fl = np.zeros((1, n, 1), np.uint8)
+    y = np.arange(n)
+    u = np.zeros((3, 1, n, 1))
+    u[0, 0, :, 0] = u0 * np.sin(2 * np.pi * y / n)
+    f = orc.init_fields(fl, None, u)
+    st, f = orc.step(fl, f, orc.rates_vector(1 / tau), 60, periodic=7)
+    assert st == 0
+    pre = orc.stream(fl, f, periodic=7)
+    rho, uu = orc.moments(fl, pre)
+    sig = orc.stress(fl, pre, 1 / tau)
+    k = 2 * np.pi / n
+    a = np.sum(uu[0, 0, :, 0] * np.sin(k * y)) * 2 / n
+    nu = (tau - 0.5) / 3
+    expect = rho[0, :, 0] * nu * a * k * np.cos(k * y)
+    err = np.abs(sig[3, 0, :, 0] - expect).max() / np.abs(expect).max()
+    assert err < 0.02
+    assert np.abs(sig[[0, 1, 2, 4, 5]]).max() < 0.02 * np.abs(expect).max()
