@@ -9,7 +9,8 @@
  * App. A, Eqs. (A.4)-(A.6), relaxation rates as stated after Eq. (8) and in
  * App. A, on the D3Q27 stencil of App. A, Eqs. (A.1)-(A.2); halfway
  * bounce-back walls, a moving-wall velocity inlet (profile of Sec. 2.2,
- * Eq. (12)) and a zero-gradient outlet.  Each step gives exactly the pull
+ * Eq. (12)) and a zero-gradient or constant-pressure (non-equilibrium
+ * extrapolation, Sec. 2.2) outlet.  Each step gives exactly the pull
  * update (every cell gathers f_i from x - c_i, then collides); the library
  * runs it in place on a single population array, alternating a streaming
  * step and a local step so that every step reads and writes the same slots.
@@ -57,8 +58,9 @@ enum lbm_flag {
     LBM_FLUID = 0,  /* updated every step */
     LBM_SOLID = 1,  /* wall: links into it are halfway bounce-back */
     LBM_INLET = 2,  /* moving wall carrying the inlet velocity; never updated */
-    LBM_OUTLET = 3  /* fluid cell on the last x plane with a zero-gradient
-                       outlet: sources beyond x = nx-1 are taken from
+    LBM_OUTLET = 3  /* fluid cell on the last x plane with an outlet (zero
+                       gradient unless lbm_set_outlet selects constant
+                       pressure): sources beyond x = nx-1 are taken from
                        x = nx-1 (same y, z shift); updated every step */
 };
 
@@ -76,6 +78,12 @@ enum lbm_status {
     LBM_ERR_DEVICE = -3,   /* a HIP runtime call failed */
     LBM_ERR_UNSTABLE = -4, /* a step produced rho <= 0 or a non-finite value */
     LBM_ERR_STATE = -5     /* call not valid in the current state */
+};
+
+/* Outlet conditions (lbm_set_outlet). */
+enum lbm_outlet {
+    LBM_OUTLET_ZERO_GRADIENT = 0, /* sources beyond the last plane copy it (default) */
+    LBM_OUTLET_PRESSURE = 1       /* constant pressure rho_out/3, non-equilibrium extrapolation */
 };
 
 /* Periodicity bits. */
@@ -159,6 +167,23 @@ int lbm_set_rates(lbm_domain *d, double omega, double omega_bulk, double omega_h
  * of range, LBM_ERR_STATE for a domain resident in a batch.
  */
 int lbm_set_order_rates(lbm_domain *d, double omega3, double omega4, double omega5, double omega6);
+
+/*
+ * Outlet condition of the LBM_OUTLET cells (Sec. 2.2, constant outlet
+ * pressure by non-equilibrium extrapolation).
+ *   kind     LBM_OUTLET_ZERO_GRADIENT: a population pulled from beyond the
+ *            last plane x = nx-1 is the post-collision value f*_i(s) of the
+ *            last-plane cell s = (nx-1, y - c_y, z - c_z) it faces.
+ *            LBM_OUTLET_PRESSURE: it is the value of a ghost cell with the
+ *            velocity u_s and the non-equilibrium part of s and the density
+ *            rho_out, f*_i(s) + (rho_out - rho_s) f^eq_i(1, u_s).
+ *   rho_out  outlet density (pressure rho_out/3), > 0; ignored for the
+ *            zero-gradient kind.
+ * Takes effect at the next step; the current state is kept.  Errors:
+ * LBM_ERR_ARG for an unknown kind or rho_out <= 0, LBM_ERR_STATE for a
+ * domain resident in a batch.
+ */
+int lbm_set_outlet(lbm_domain *d, int kind, double rho_out);
 
 /*
  * Inlet velocity (Sec. 2.2, Eq. (12) profile, or any field).

@@ -359,13 +359,30 @@ typedef struct {
 
 static int updatable(uint8_t fl) { return fl == F_FLUID || fl == F_OUTLET; }
 
+/* Outlet condition: 0 zero gradient, 1 constant pressure by
+ * non-equilibrium extrapolation (Sec. 2.2, "Simulation details").
+ * Reading for the constant-pressure outlet: the ghost cell beyond the last
+ * x plane has the velocity and the non-equilibrium part of the last-plane
+ * cell it faces and the outlet density rho_out, so a population pulled
+ * from it is f*_i(s) - f^eq_i(rho_s, u_s) + f^eq_i(rho_out, u_s) with s the
+ * clamped last-plane source and rho_s, u_s its moments. */
+static int g_outlet_kind = 0;
+static double g_rho_out = 1.0;
+
+void oracle_set_outlet(int kind, double rho_out)
+{
+    g_outlet_kind = kind;
+    g_rho_out = rho_out;
+}
+
 static int wrap(int s, int n) { return ((s % n) + n) % n; }
 
 /* Resolve the source of population i at cell (x,y,z).  Returns the kind
  * of link: 0 plain pull from *src, 1 wall (halfway bounce-back), 2 inlet
  * (moving-wall bounce-back; *src is the inlet cell). */
-static int resolve(const odom *d, int x, int y, int z, int i, long *src)
+static int resolve(const odom *d, int x, int y, int z, int i, long *src, int *clamped)
 {
+    *clamped = 0;
     int sx = x - g_c[i][0], sy = y - g_c[i][1], sz = z - g_c[i][2];
     if (d->periodic & 1u)
         sx = wrap(sx, d->nx);
@@ -375,8 +392,10 @@ static int resolve(const odom *d, int x, int y, int z, int i, long *src)
         sz = wrap(sz, d->nz);
     long self = ((long)z * d->ny + y) * d->nx + x;
     /* zero-gradient outlet: sources past the last x plane come from it */
-    if (sx >= d->nx && !(d->periodic & 1u) && d->flags[self] == F_OUTLET)
+    if (sx >= d->nx && !(d->periodic & 1u) && d->flags[self] == F_OUTLET) {
         sx = d->nx - 1;
+        *clamped = 1;
+    }
     if (sx < 0 || sx >= d->nx || sy < 0 || sy >= d->ny || sz < 0 || sz >= d->nz)
         return 1;
     long s = ((long)sz * d->ny + sy) * d->nx + sx;
@@ -395,9 +414,18 @@ static void gather_cell(const odom *d, const double *f, long cell, double *g)
     int x = (int)(cell % d->nx), y = (int)((cell / d->nx) % d->ny), z = (int)(cell / ((long)d->nx * d->ny));
     for (int i = 0; i < NQ; ++i) {
         long src = cell;
-        int kind = resolve(d, x, y, z, i, &src);
+        int clamped = 0;
+        int kind = resolve(d, x, y, z, i, &src, &clamped);
         if (kind == 0) {
             g[i] = f[(long)i * d->ncells + src];
+            if (clamped && g_outlet_kind == 1) {
+                double fs[NQ], rs = 0.0, us[3] = {0.0, 0.0, 0.0}, fe[NQ];
+                for (int k = 0; k < NQ; ++k)
+                    fs[k] = f[(long)k * d->ncells + src];
+                oracle_cell_moments(fs, &rs, us);
+                oracle_feq(1.0, us, 6, fe); /* f^eq is linear in rho */
+                g[i] += (g_rho_out - rs) * fe[i];
+            }
         } else {
             double v = f[(long)(NQ - 1 - i) * d->ncells + cell];
             if (kind == 2) {
@@ -622,7 +650,8 @@ int oracle_run_cells(const uint8_t *flags, int nx, int ny, int nz, unsigned peri
             int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((long)nx * ny));
             for (int i = 0; i < NQ; ++i) {
                 long src = cell;
-                int kind = resolve(&d, x, y, z, i, &src);
+                int clamped = 0;
+                int kind = resolve(&d, x, y, z, i, &src, &clamped);
                 prev[m++] = kind == 0 ? src : cell;
             }
         }
@@ -652,9 +681,17 @@ int oracle_run_cells(const uint8_t *flags, int nx, int ny, int nz, unsigned peri
             double g[NQ];
             for (int i = 0; i < NQ; ++i) {
                 long src = cell;
-                int kind = resolve(&d, x, y, z, i, &src);
+                int clamped = 0;
+                int kind = resolve(&d, x, y, z, i, &src, &clamped);
                 if (kind == 0) {
-                    g[i] = state[(long)NQ * find_slot(pc, npc, src) + i];
+                    const double *fs = state + (long)NQ * find_slot(pc, npc, src);
+                    g[i] = fs[i];
+                    if (clamped && g_outlet_kind == 1) {
+                        double rs = 0.0, us[3] = {0.0, 0.0, 0.0}, fe[NQ];
+                        oracle_cell_moments(fs, &rs, us);
+                        oracle_feq(1.0, us, 6, fe);
+                        g[i] += (g_rho_out - rs) * fe[i];
+                    }
                 } else {
                     double v = state[(long)NQ * self + (NQ - 1 - i)];
                     if (kind == 2) {

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
 FP32, FP16S, BF16S = 0, 1, 2
 STORAGE = {"fp32": FP32, "fp16s": FP16S, "bf16s": BF16S}
+OUTLETS = {"zero_gradient": 0, "pressure": 1}
 OK, ERR_ARG, ERR_OOM, ERR_DEVICE, ERR_UNSTABLE, ERR_STATE = 0, -1, -2, -3, -4, -5
 Q = 27
 
@@ -53,6 +54,7 @@ SIGNATURES = {
     "lbm_set_params": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_rates": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_order_rates": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "lbm_set_outlet": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double]),
     "lbm_set_inlet": (ctypes.c_int, [_vp, _fp]),
     "lbm_set_inlet_cells": (ctypes.c_int, [_vp, _fp]),
     "lbm_init_fields": (ctypes.c_int, [_vp, _fp, _fp]),
@@ -153,6 +155,10 @@ class Domain:
 
     def set_order_rates(self, omega3, omega4, omega5, omega6):
         check(lbm_set_order_rates(self.h, omega3, omega4, omega5, omega6))
+
+    def set_outlet(self, kind="zero_gradient", rho_out=1.0):
+        """Outlet condition: "zero_gradient" or "pressure" (rho_out)."""
+        check(lbm_set_outlet(self.h, OUTLETS[kind], float(rho_out)))
 
     def set_inlet(self, uin):
         a, p = _f32(uin, 3 * self.ncells)

@@ -239,6 +239,8 @@ struct lbm_domain {
     uint64_t bytes = 0;   // its size
     int phase = 0;        // phase of the stored state (k_stream_collide)
     bool outlets = false; // the domain has outlet cells
+    int outlet_kind = LBM_OUTLET_ZERO_GRADIENT;
+    double rho_out = 1.0; // outlet density of the constant-pressure outlet
     float *d_stats = nullptr;   // statistics sums, [15][64 ntiles]
     bool stats_on = false;
     uint64_t stats_samples = 0; // local steps accumulated
@@ -342,6 +344,8 @@ KDomain kdomain(const lbm_domain *d)
     k.omega_b = (float)d->omega_b;
     for (int n = 0; n < 4; ++n)
         k.omega_o[n] = (float)d->omega_o[n];
+    k.outlet = d->outlet_kind == LBM_OUTLET_PRESSURE ? 1u : 0u;
+    k.rho_out = (float)d->rho_out;
     return k;
 }
 
@@ -483,8 +487,6 @@ hipError_t normalise(lbm_domain *d)
                                (const TileRec *)d->d_tiles, (uint32_t)d->ntiles);
         });
         if (hipError_t e = hipGetLastError())
-            return e;
-        if (hipError_t e = side_refresh(d))
             return e;
     }
     d->phase = 0;
@@ -740,6 +742,24 @@ int lbm_set_order_rates(lbm_domain *d, double omega3, double omega4, double omeg
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     for (int n = 0; n < 4; ++n)
         d->omega_o[n] = w[n];
+    d->graph_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_set_outlet(lbm_domain *d, int kind, double rho_out)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (kind != LBM_OUTLET_ZERO_GRADIENT && kind != LBM_OUTLET_PRESSURE)
+        return fail(LBM_ERR_ARG, "unknown outlet kind %d", kind);
+    if (!(rho_out > 0) || !std::isfinite(rho_out))
+        return fail(LBM_ERR_ARG, "rho_out must be positive and finite");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    HIP_TRY(normalise(d));
+    d->outlet_kind = kind;
+    d->rho_out = rho_out;
+    HIP_TRY(side_refresh(d));
     d->graph_dirty = true;
     return LBM_OK;
 }

@@ -99,6 +99,8 @@ struct KDomain {
     // batched execution: the domain takes part in global steps
     // [step0, step0 + nsteps), starting in phase ph0.
     uint32_t step0, nsteps, ph0, pad;
+    uint32_t outlet;         // 0: zero-gradient outlet, 1: constant pressure rho_out / 3
+    float rho_out;
 };
 
 // One entry of a tile list (48 bytes; a wave reads it with scalar loads).
@@ -541,6 +543,27 @@ __device__ __forceinline__ float inlet_term(const KDomain &d, const TileRec &rec
                                                                 (uint32_t)k * 256u, 0));
 }
 
+// Constant-pressure outlet by non-equilibrium extrapolation (Sec. 2.2): the
+// ghost cell beyond the last plane has the velocity and non-equilibrium part
+// of the last-plane cell s it faces and the density rho_out.  Its value of
+// direction k = 3 j (c_x = -1) is f*_k(s) + (rho_out - rho_s) f^eq_k(1, u_s),
+// f^eq being linear in rho; g[j] receives the second term, with f^eq(1, u)
+// in product form, prod_a phi(c_a, u_a), phi(0, u) = 2/3 - u^2,
+// phi(+-1, u) = (1 +- 3u + 3u^2)/6.  rho_s and u_s are the moments of s,
+// which its collision keeps.
+__device__ __forceinline__ void outlet_ghost_shift(const KDomain &d, float rho, float ux, float uy, float uz,
+                                                   float (&g)[9])
+{
+    const float a = (d.rho_out - rho) * (1.f / 6.f) * (1.f - 3.f * ux + 3.f * ux * ux);
+    const float py[3] = {(1.f / 6.f) * (1.f - 3.f * uy + 3.f * uy * uy), 2.f / 3.f - uy * uy,
+                         (1.f / 6.f) * (1.f + 3.f * uy + 3.f * uy * uy)};
+    const float pz[3] = {(1.f / 6.f) * (1.f - 3.f * uz + 3.f * uz * uz), 2.f / 3.f - uz * uz,
+                         (1.f / 6.f) * (1.f + 3.f * uz + 3.f * uz * uz)};
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+        g[j] = a * py[j % 3] * pz[j / 3];
+}
+
 // Byte offset of slot a_k of the lane whose coordinates are C: the plain
 // neighbour slot, or for a c_x = -1 link of a cell on the outlet plane of
 // an edge tile the side row named by h (0: the clamped upstream value to
@@ -624,6 +647,9 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
     if (edge_lane) {
         // last-plane cell: hand the clamped values to the outlet cells it
         // feeds, cell (nx - 1, y + c_y, z + c_z) for direction k = 3 j
+        float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (d.outlet)
+            outlet_ghost_shift(d, rho, ux, uy, uz, g);
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
             const int k = 3 * j;
@@ -631,7 +657,7 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
             if (plane_step(C.y, cy(k), d.ny, d.periodic & 2u, ty) && plane_step(C.z, cz(k), d.nz, d.periodic & 4u, tz)) {
                 const uint32_t t = (tz * d.ny + ty) * d.nx + d.nx - 1u;
                 if (d.flags[t] == FL_OUTLET)
-                    S::store(r, cell_bytes<es>(t, d.tbytes), pop_bytes<es>(k), f[k], k);
+                    S::store(r, cell_bytes<es>(t, d.tbytes), pop_bytes<es>(k), d.outlet ? f[k] + g[j] : f[k], k);
             }
         }
     }
@@ -729,9 +755,13 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
         if (lin - q * d.nx == d.nx - 1u) {
             // last-plane cell: its c_x = -1 values for the outlet cells
             const uint32_t z = fdiv(q, d.dny), y = q - z * d.ny;
+            float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (d.outlet)
+                outlet_ghost_shift(d, rho, ux, uy, uz, g);
 #pragma unroll
             for (int j = 0; j < 9; ++j)
-                S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, f[3 * j], 3 * j);
+                S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, d.outlet ? f[3 * j] + g[j] : f[3 * j],
+                         3 * j);
         }
     }
 }
@@ -858,9 +888,12 @@ __global__ void k_advance_step(uint32_t *ctrl)
 
 // Phase 1 -> 0 without a collision: every slot pair (x, k) / a_k(x) of a
 // link that is neither bounced back nor clamped swaps its two values; a
-// bounce-back slot loses its inlet term; the clamped slots of an outlet
-// cell take the leaving values parked in the second side rows.  The first
-// side rows are refreshed afterwards (k_side_refresh).
+// bounce-back slot loses its inlet term; a clamped slot of an outlet cell
+// hands the value it received (the ghost value of its source cell s) to
+// the first side row of s, where the next streaming step reads it, and
+// takes the leaving value parked in the second side row.  Every side-row
+// entry a streaming step reads is rewritten that way, by the one outlet
+// cell that reads it.
 template <int ST>
 __global__ __launch_bounds__(256) void k_normalise(KDomain d, const TileRec *__restrict__ tiles, uint32_t ntiles)
 {
@@ -886,6 +919,7 @@ __global__ __launch_bounds__(256) void k_normalise(KDomain d, const TileRec *__r
                 S::store(r, self, pop_bytes<es>(k), v, k);
             }
         } else if (edge_lane && k % 3 == 0) {
+            S::store_raw(r, slot_of<es>(d, C, k, true, 0u), 0u, S::raw(r, self + pop_bytes<es>(k), 0u));
             S::store_raw(r, self + pop_bytes<es>(k), 0u, S::raw(r, slot_of<es>(d, C, k, true, 1u), 0u));
         } else if (k > Q / 2) {
             const uint32_t ak = cell_bytes<es>(C.row[k / 3] + C.sx[k % 3], d.tbytes) + pop_bytes<es>(Q - 1 - k);
@@ -896,8 +930,10 @@ __global__ __launch_bounds__(256) void k_normalise(KDomain d, const TileRec *__r
     }
 }
 
-// First side rows from a phase-0 state: f*_k of each updated last-plane
-// cell for k = 3 j, i.e. slot (x, 26 - 3 j).  One lane per (y, z).
+// First side rows from a phase-0 state (after an initialisation or an
+// import): the ghost value of each updated last-plane cell for k = 3 j,
+// f*_k from slot (x, 26 - 3 j), plus the pressure outlet's shift.  One lane
+// per (y, z).
 template <int ST>
 __global__ __launch_bounds__(256) void k_side_refresh(KDomain d)
 {
@@ -912,8 +948,26 @@ __global__ __launch_bounds__(256) void k_side_refresh(KDomain d)
         return;
     const auto r = make_rsrc(d.buf, d.bufbytes);
     const uint32_t cb = cell_bytes<es>(c, d.tbytes);
+    if (!d.outlet) {
+        for (int j = 0; j < 9; ++j)
+            S::store_raw(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u,
+                         S::raw(r, cb + pop_bytes<es>(Q - 1 - 3 * j), 0u));
+        return;
+    }
+    float f[Q], rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        f[i] = S::load(r, cb, pop_bytes<es>(Q - 1 - i), i);
+        rho += f[i];
+        jx += (float)cx(i) * f[i];
+        jy += (float)cy(i) * f[i];
+        jz += (float)cz(i) * f[i];
+    }
+    float g[9];
+    outlet_ghost_shift(d, rho, jx / rho, jy / rho, jz / rho, g);
+#pragma unroll
     for (int j = 0; j < 9; ++j)
-        S::store_raw(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, S::raw(r, cb + pop_bytes<es>(Q - 1 - 3 * j), 0u));
+        S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, f[3 * j] + g[j], 3 * j);
 }
 
 // f = f^eq(rho, u) in product form: the sixth-order Hermite equilibrium of

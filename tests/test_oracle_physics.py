@@ -6,7 +6,11 @@ mass and momentum are conserved to round-off.  Physical pins with a stated
 tolerance: viscous decay of a Taylor-Green vortex and of a wall-bounded shear
 wave at nu = theta0 (tau - 1/2) (Sec. 2.1, Eq. (5)); a velocity-inlet /
 zero-gradient outlet passing a uniform stream unchanged, and the inlet
-injecting exactly its prescribed mass flux (Sec. 2.2, "Simulation details")."""
+injecting exactly its prescribed mass flux (Sec. 2.2, "Simulation details").
+The constant-pressure outlet (non-equilibrium extrapolation, Sec. 2.2): the
+mass and momentum a uniform field receives from it in one step in closed
+form, and a stream that settles at the outlet density with the inflow's
+mass flux."""
 import math
 
 import numpy as np
@@ -202,6 +206,84 @@ def test_inlet_injects_exact_mass_flux(orc):
         assert abs(f[:, upd].sum() - m0 - s * expect) < 1e-12
 
 
+def uniform_outlet_box(nx, ny, nz):
+    fl = np.zeros((nz, ny, nx), np.uint8)
+    fl[:, :, -1] = I.OUTLET
+    return fl
+
+
+@pytest.mark.parametrize("rho_s,rho_out", [(1.0, 1.02), (1.03, 0.99)])
+def test_pressure_outlet_one_step_closed_form(orc, rho_s, rho_out):
+    """Every cell holds f^eq(rho_s, u).  An outlet-plane cell then pulls
+    f^eq_i(rho_s, u) across the interior and, through each of the nine links
+    from beyond the last plane (c_x = -1), the ghost value f^eq_i(rho_out, u)
+    of non-equilibrium extrapolation; collision keeps the pulled mass and
+    momentum, so after one step rho = rho_s + (rho_out - rho_s) W and
+    j = rho_s u + (rho_out - rho_s) J with W, J the mass and momentum of the
+    nine ghost directions of f^eq(1, u).  The zero-gradient outlet keeps
+    rho_s."""
+    nx, ny, nz = 5, 3, 4
+    fl = uniform_outlet_box(nx, ny, nz)
+    u = np.array([0.04, -0.02, 0.015])
+    f = orc.init_fields(fl, np.full(fl.shape, rho_s), np.broadcast_to(u[:, None, None, None], (3,) + fl.shape))
+    e1 = orc.feq(1.0, u)
+    ghost = C[:, 0] == -1
+    W = e1[ghost].sum()
+    J = (C[ghost] * e1[ghost, None]).sum(axis=0)
+    rates = orc.rates_vector(1 / 0.8, 1.1, 1.0)
+    for outlet, r_exp, j_exp in [(("pressure", rho_out), rho_s + (rho_out - rho_s) * W,
+                                  rho_s * u + (rho_out - rho_s) * J),
+                                 (None, rho_s, rho_s * u)]:
+        st, g = orc.step(fl, f, rates, 1, periodic=6, outlet=outlet)
+        rho, uu = orc.moments(fl, g)
+        assert st == 0
+        assert np.abs(rho[:, :, -1] - r_exp).max() < 1e-14
+        assert np.abs(rho[:, :, -1, None] * np.moveaxis(uu[:, :, :, -1], 0, -1) - j_exp).max() < 1e-14
+        # one cell in from the outlet nothing changes
+        assert np.abs(g[:, :, :, 1:-1] - f[:, :, :, 1:-1]).max() < 1e-15
+
+
+def test_pressure_outlet_at_reference_density_keeps_plug_flow(orc):
+    """With rho_out = 1 the ghost of a uniform f^eq(1, u_in) stream is the
+    stream itself, so the plug flow stays a fixed point."""
+    nx, ny, nz, u0 = 12, 3, 2, 0.03
+    fl = plug_box(nx, ny, nz)
+    uin = np.zeros((3, nz, ny, nx))
+    uin[0, :, :, 0] = u0
+    u = np.zeros((3, nz, ny, nx))
+    u[0][fl != I.INLET] = u0
+    f = orc.init_fields(fl, None, u)
+    st, g = orc.step(fl, f, orc.rates_vector(1 / 0.7, 1.2, 1.0), 50, periodic=6, uin=uin,
+                     outlet=("pressure", 1.0))
+    upd = fl != I.INLET
+    assert st == 0 and np.abs(g[:, upd] - f[:, upd]).max() < 1e-15
+
+
+def test_pressure_outlet_sets_density_and_passes_inflow(orc):
+    """A stream entering at u_in through the moving-wall inlet (rho_w = 1)
+    and leaving through the pressure outlet settles, once the acoustic
+    transient has decayed, at the outlet density everywhere, carrying the
+    inflow mass flux u_in.  The zero-gradient outlet leaves the density at
+    its initial value 1."""
+    nx, u0, rho_out, tau = 24, 0.03, 1.01, 2.0
+    fl = plug_box(nx, 1, 1)
+    uin = np.zeros((3, 1, 1, nx))
+    uin[0, :, :, 0] = u0
+    u = np.zeros((3, 1, 1, nx))
+    u[0][fl != I.INLET] = u0
+    f = orc.init_fields(fl, None, u)
+    rates = orc.rates_vector(1 / tau, 1 / tau, 1.0)
+    st, g = orc.step(fl, f, rates, 3000, periodic=6, uin=uin, outlet=("pressure", rho_out))
+    rho, uu = orc.moments(fl, g)
+    assert st == 0
+    assert np.abs(rho[0, 0, 1:] - rho_out).max() < 2e-6
+    assert np.abs((rho * uu[0])[0, 0, 1:] - u0).max() < 5e-6
+    assert np.abs(uu[1:]).max() < 1e-12
+    st, g = orc.step(fl, f, rates, 3000, periodic=6, uin=uin)
+    rho, _ = orc.moments(fl, g)
+    assert np.abs(rho[0, 0, 1:] - 1.0).max() < 1e-12
+
+
 def test_unstable_state_reported(orc):
     """A negative-density state is reported as unstable, not hidden."""
     fl = np.zeros((2, 2, 2), np.uint8)
@@ -210,19 +292,20 @@ def test_unstable_state_reported(orc):
     assert st == orc.ERR_UNSTABLE
 
 
-def test_run_cells_matches_full_step(orc):
+@pytest.mark.parametrize("outlet", [None, ("pressure", 1.004)])
+def test_run_cells_matches_full_step(orc, outlet):
     """The sampled (dependency-cone) run equals the full-field run at the
     listed cells, on a small nozzle with inlet, walls and outlet."""
     cfg = I.small_nozzle(n=12, length=40, R=5.0, r_throat=2.5)
     fl = cfg["flags"]
     rates = orc.rates_vector(1 / cfg["tau"], 1 / cfg["tau"], 1.0)
     f0 = orc.init_fields(fl, None, cfg["u0"])
-    st, f = orc.step(fl, f0, rates, 3, periodic=0, uin=cfg["uin"])
+    st, f = orc.step(fl, f0, rates, 3, periodic=0, uin=cfg["uin"], outlet=outlet)
     assert st == 0
     upd = np.flatnonzero((fl.ravel() == 0) | (fl.ravel() == 3))
     rng = np.random.default_rng(0)
     cells = np.concatenate([upd[:5], upd[-5:], rng.choice(upd, 30, replace=False)])
-    st, fc = orc.run_cells(fl, cells, rates, 3, periodic=0, uin=cfg["uin"], u0=cfg["u0"])
+    st, fc = orc.run_cells(fl, cells, rates, 3, periodic=0, uin=cfg["uin"], u0=cfg["u0"], outlet=outlet)
     assert st == 0
     assert np.array_equal(fc, f.reshape(27, -1)[:, cells])
 
