@@ -8,7 +8,8 @@
  * Eqs. (7)-(8), the full (sixth-order) Hermite equilibrium of Eq. (4) and
  * App. A, Eqs. (A.4)-(A.6), relaxation rates as stated after Eq. (8) and in
  * App. A, on the D3Q27 stencil of App. A, Eqs. (A.1)-(A.2); halfway
- * bounce-back walls, a moving-wall velocity inlet (profile of Sec. 2.2,
+ * bounce-back walls (halfway, or interpolated for curved walls), a
+ * moving-wall velocity inlet (profile of Sec. 2.2,
  * Eq. (12)) and a zero-gradient or constant-pressure (non-equilibrium
  * extrapolation, Sec. 2.2) outlet.  Each step gives exactly the pull
  * update (every cell gathers f_i from x - c_i, then collides); the library
@@ -184,6 +185,27 @@ int lbm_set_order_rates(lbm_domain *d, double omega3, double omega4, double omeg
  * domain resident in a batch.
  */
 int lbm_set_outlet(lbm_domain *d, int kind, double rho_out);
+
+/*
+ * Curved walls (Sec. 2.2: no-slip walls by the interpolated bounce-back of
+ * Bouzidi, Firdaouss and Lallemand, linear form).
+ *   q  host, 27*ncells floats, layout [i][cell], or NULL for the halfway
+ *      rule everywhere (the default).  q[i][x] is read only where link i of
+ *      an updated cell x is a wall link (x - c_i is LBM_SOLID or outside a
+ *      non-periodic box): the fraction of the link, from x towards x - c_i,
+ *      at which the wall lies, in (0, 1].  With f* the post-collision
+ *      populations of the previous step and ibar the opposite of i:
+ *        q <  1/2: f_i(x) = 2q f*_ibar(x) + (1 - 2q) f*_ibar(x + c_i)
+ *        q >= 1/2: f_i(x) = f*_ibar(x)/(2q) + (1 - 1/(2q)) f*_i(x)
+ *      q = 1/2 is the halfway rule; so is q < 1/2 when the link x -> x + c_i
+ *      is not a plain link (a gap one cell wide, an inlet behind it).
+ * Takes effect at the next step; the state is kept.  Device memory: 12 bytes
+ * per link slot of the wall tiles (27*64 per wall tile), only while some q
+ * differs from 1/2.  Errors: LBM_ERR_ARG for a fraction outside (0, 1] at a
+ * wall link (nothing changed), LBM_ERR_STATE for a domain resident in a
+ * batch, LBM_ERR_OOM.
+ */
+int lbm_set_wall_distances(lbm_domain *d, const float *q);
 
 /*
  * Inlet velocity (Sec. 2.2, Eq. (12) profile, or any field).

@@ -71,6 +71,7 @@ def lib():
         L.oracle_moments.argtypes = [u8p, ctypes.c_long, dp, dp, dp]
         L.oracle_stress.argtypes = [u8p, ctypes.c_long, dp, ctypes.c_double, dp]
         L.oracle_set_outlet.argtypes = [ctypes.c_int, ctypes.c_double]
+        L.oracle_set_wall_distances.argtypes = [dp]
         L.oracle_run_cells.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, dp, dp, dp,
                                        dp, ctypes.c_int, ctypes.c_long, lp, dp]
         L.oracle_run_cells.restype = ctypes.c_int
@@ -168,13 +169,13 @@ def init_fields(flags, rho=None, u=None):
     return f
 
 
-def stream(flags, f, periodic=0, uin=None, outlet=None):
+def stream(flags, f, periodic=0, uin=None, outlet=None, q=None):
     """Pull streaming pass with the boundary rules of Sec. 2.2."""
     fl, flp = _u8(flags)
     nz, ny, nx = fl.shape
     fa = _f64(f)
     g = np.zeros_like(fa)
-    with _outlet(outlet):
+    with _boundary(flags, outlet, q):
         lib().oracle_stream(flp, nx, ny, nz, periodic, _dp(_f64(uin)), _dp(fa), _dp(g))
     return g
 
@@ -186,14 +187,14 @@ def collide_field(flags, f, rates):
     return st, fa
 
 
-def step(flags, f, rates, nsteps=1, periodic=0, uin=None, outlet=None):
+def step(flags, f, rates, nsteps=1, periodic=0, uin=None, outlet=None, q=None):
     """nsteps of stream + collide.  Returns (status, f_new)."""
     fl, flp = _u8(flags)
     nz, ny, nx = fl.shape
     fa = _f64(f).copy()
     work = np.empty_like(fa)
     uin_a = _f64(uin)
-    with _outlet(outlet):
+    with _boundary(flags, outlet, q):
         st = lib().oracle_step(flp, nx, ny, nz, periodic, _dp(uin_a), _dp(_f64(rates)), int(nsteps), _dp(fa),
                                _dp(work))
     return st, fa
@@ -212,21 +213,29 @@ def moments(flags, f):
 OUTLETS = {"zero_gradient": 0, "pressure": 1}
 
 
-class _outlet:
-    """Selects the outlet condition (Sec. 2.2) for the duration of one call:
-    None or "zero_gradient" copies the last plane; ("pressure", rho_out)
-    holds the outlet pressure at rho_out / 3 by non-equilibrium
-    extrapolation."""
+class _boundary:
+    """Selects the boundary options of Sec. 2.2 for the duration of one
+    call.  outlet: None or "zero_gradient" copies the last plane;
+    ("pressure", rho_out) holds the outlet pressure at rho_out / 3 by
+    non-equilibrium extrapolation.  q: None (halfway bounce-back) or the
+    wall fraction of every link, [27, nz, ny, nx], read at wall links."""
 
-    def __init__(self, outlet):
+    def __init__(self, flags, outlet=None, q=None):
         kind, rho = ("zero_gradient", 1.0) if outlet in (None, "zero_gradient") else outlet
         self.args = (OUTLETS[kind], float(rho))
+        self.q = None
+        if q is not None:
+            self.q = np.ascontiguousarray(q, dtype=np.float64).reshape(NQ, -1)
+            if self.q.shape[1] != np.asarray(flags).size:
+                raise ValueError("q must hold 27 values per cell")
 
     def __enter__(self):
         lib().oracle_set_outlet(*self.args)
+        lib().oracle_set_wall_distances(_dp(self.q))
 
     def __exit__(self, *exc):
         lib().oracle_set_outlet(0, 1.0)
+        lib().oracle_set_wall_distances(None)
 
 
 def stress(flags, f, omega):
@@ -240,7 +249,7 @@ def stress(flags, f, omega):
     return sig
 
 
-def run_cells(flags, cells, rates, nsteps, periodic=0, uin=None, rho0=None, u0=None, outlet=None):
+def run_cells(flags, cells, rates, nsteps, periodic=0, uin=None, rho0=None, u0=None, outlet=None, q=None):
     """Populations after nsteps at the listed linear cell indices, starting
     from f^eq(rho0, u0); only the dependency cone is computed.  Returns
     (status, f[27, len(cells)])."""
@@ -248,7 +257,7 @@ def run_cells(flags, cells, rates, nsteps, periodic=0, uin=None, rho0=None, u0=N
     nz, ny, nx = fl.shape
     cl = np.ascontiguousarray(cells, dtype=np.int64)
     out = np.zeros((NQ, cl.size))
-    with _outlet(outlet):
+    with _boundary(flags, outlet, q):
         st = lib().oracle_run_cells(flp, nx, ny, nz, periodic, _dp(_f64(uin)), _dp(_f64(rho0)), _dp(_f64(u0)),
                                     _dp(_f64(rates)), int(nsteps), cl.size,
                                     cl.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _dp(out))

@@ -407,38 +407,88 @@ static int resolve(const odom *d, int x, int y, int z, int i, long *src, int *cl
     return 0;
 }
 
+/* Curved walls (Sec. 2.2, interpolated bounce-back after Bouzidi et al.):
+ * q[i*ncells + cell] is the fraction of the link from cell x towards
+ * x - c_i at which the wall lies, read for wall links only; NULL keeps the
+ * halfway rule (q = 1/2 everywhere).  With f* the post-collision field of
+ * the previous step the linear interpolation gives
+ *   q <  1/2: f_i(x) = 2q f*_ibar(x) + (1 - 2q) f*_ibar(x + c_i),
+ *   q >= 1/2: f_i(x) = f*_ibar(x) / (2q) + (1 - 1/(2q)) f*_i(x),
+ * ibar the opposite direction.  f*_ibar(x + c_i) is the value x pulls for
+ * direction ibar.  Reading for a cell whose opposite link ibar is not a
+ * plain link (a gap one cell wide, or an inlet behind it): with q < 1/2
+ * the halfway rule is kept. */
+static const double *g_q = NULL;
+
+void oracle_set_wall_distances(const double *q) { g_q = q; }
+
+/* Post-collision population i of cell `cell` of the previous step. */
+typedef double (*pop_fn)(const void *ctx, long cell, int i);
+
+/* Pre-collision populations g of one updatable cell. */
+static void pull_cell(const odom *d, long cell, pop_fn pop, const void *ctx, double *g)
+{
+    int x = (int)(cell % d->nx), y = (int)((cell / d->nx) % d->ny), z = (int)(cell / ((long)d->nx * d->ny));
+    int kind[NQ];
+    long src[NQ];
+    /* plain links first: the curved-wall rule reads them */
+    for (int i = 0; i < NQ; ++i) {
+        int clamped = 0;
+        src[i] = cell;
+        kind[i] = resolve(d, x, y, z, i, &src[i], &clamped);
+        if (kind[i] != 0)
+            continue;
+        g[i] = pop(ctx, src[i], i);
+        if (clamped && g_outlet_kind == 1) {
+            double fs[NQ], rs = 0.0, us[3] = {0.0, 0.0, 0.0}, fe[NQ];
+            for (int k = 0; k < NQ; ++k)
+                fs[k] = pop(ctx, src[i], k);
+            oracle_cell_moments(fs, &rs, us);
+            oracle_feq(1.0, us, 6, fe); /* f^eq is linear in rho */
+            g[i] += (g_rho_out - rs) * fe[i];
+        }
+    }
+    for (int i = 0; i < NQ; ++i) {
+        if (kind[i] == 0)
+            continue;
+        double v = pop(ctx, cell, NQ - 1 - i);
+        if (kind[i] == 2) {
+            double cu = 0.0;
+            if (d->uin)
+                for (int a = 0; a < 3; ++a)
+                    cu += g_c[i][a] * d->uin[(long)a * d->ncells + src[i]];
+            /* wall density 1: + 2 w_i (c_i . u_w) / theta0 */
+            v += 2.0 * g_w[i] * cu / THETA0;
+        } else if (g_q) {
+            double q = g_q[(long)i * d->ncells + cell];
+            if (q < 0.5) {
+                if (kind[NQ - 1 - i] == 0)
+                    v = 2.0 * q * v + (1.0 - 2.0 * q) * g[NQ - 1 - i];
+            } else {
+                v = v / (2.0 * q) + (1.0 - 1.0 / (2.0 * q)) * pop(ctx, cell, i);
+            }
+        }
+        g[i] = v;
+    }
+}
+
+typedef struct {
+    const double *f;
+    long ncells;
+} field_ctx;
+
+static double field_pop(const void *ctx, long cell, int i)
+{
+    const field_ctx *c = (const field_ctx *)ctx;
+    return c->f[(long)i * c->ncells + cell];
+}
+
 /* Pre-collision populations g of one updatable cell from the
  * post-collision field f of the previous step. */
 static void gather_cell(const odom *d, const double *f, long cell, double *g)
 {
-    int x = (int)(cell % d->nx), y = (int)((cell / d->nx) % d->ny), z = (int)(cell / ((long)d->nx * d->ny));
-    for (int i = 0; i < NQ; ++i) {
-        long src = cell;
-        int clamped = 0;
-        int kind = resolve(d, x, y, z, i, &src, &clamped);
-        if (kind == 0) {
-            g[i] = f[(long)i * d->ncells + src];
-            if (clamped && g_outlet_kind == 1) {
-                double fs[NQ], rs = 0.0, us[3] = {0.0, 0.0, 0.0}, fe[NQ];
-                for (int k = 0; k < NQ; ++k)
-                    fs[k] = f[(long)k * d->ncells + src];
-                oracle_cell_moments(fs, &rs, us);
-                oracle_feq(1.0, us, 6, fe); /* f^eq is linear in rho */
-                g[i] += (g_rho_out - rs) * fe[i];
-            }
-        } else {
-            double v = f[(long)(NQ - 1 - i) * d->ncells + cell];
-            if (kind == 2) {
-                double cu = 0.0;
-                if (d->uin)
-                    for (int a = 0; a < 3; ++a)
-                        cu += g_c[i][a] * d->uin[(long)a * d->ncells + src];
-                /* wall density 1: + 2 w_i (c_i . u_w) / theta0 */
-                v += 2.0 * g_w[i] * cu / THETA0;
-            }
-            g[i] = v;
-        }
-    }
+    field_ctx c = {f, d->ncells};
+    pull_cell(d, cell, field_pop, &c, g);
 }
 
 /* Pull streaming pass over the whole field: g = stream(f).  Cells that
@@ -622,6 +672,19 @@ static long unique_sorted(long *a, long n)
     return m;
 }
 
+/* States of the previous step of the listed cells (sorted), 27 each. */
+typedef struct {
+    const double *state;
+    const long *cells;
+    long n;
+} cone_ctx;
+
+static double cone_pop(const void *ctx, long cell, int i)
+{
+    const cone_ctx *c = (const cone_ctx *)ctx;
+    return c->state[(long)NQ * find_slot(c->cells, c->n, cell) + i];
+}
+
 int oracle_run_cells(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, const double *uin,
                      const double *rho0, const double *u0, const double *rates, int nsteps, long nlist,
                      const long *list, double *out /* 27*nlist, [i][k] */)
@@ -676,34 +739,9 @@ int oracle_run_cells(const uint8_t *flags, int nx, int ny, int nz, unsigned peri
 #pragma omp parallel for schedule(dynamic, 64)
         for (long k = 0; k < nneed[t]; ++k) {
             long cell = need[t][k];
-            int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((long)nx * ny));
-            long self = find_slot(pc, npc, cell);
             double g[NQ];
-            for (int i = 0; i < NQ; ++i) {
-                long src = cell;
-                int clamped = 0;
-                int kind = resolve(&d, x, y, z, i, &src, &clamped);
-                if (kind == 0) {
-                    const double *fs = state + (long)NQ * find_slot(pc, npc, src);
-                    g[i] = fs[i];
-                    if (clamped && g_outlet_kind == 1) {
-                        double rs = 0.0, us[3] = {0.0, 0.0, 0.0}, fe[NQ];
-                        oracle_cell_moments(fs, &rs, us);
-                        oracle_feq(1.0, us, 6, fe);
-                        g[i] += (g_rho_out - rs) * fe[i];
-                    }
-                } else {
-                    double v = state[(long)NQ * self + (NQ - 1 - i)];
-                    if (kind == 2) {
-                        double cu = 0.0;
-                        if (uin)
-                            for (int a = 0; a < 3; ++a)
-                                cu += g_c[i][a] * uin[(long)a * d.ncells + src];
-                        v += 2.0 * g_w[i] * cu / THETA0;
-                    }
-                    g[i] = v;
-                }
-            }
+            cone_ctx c = {state, pc, npc};
+            pull_cell(&d, cell, cone_pop, &c, g);
             int st = oracle_collide(g, rates, next + (long)NQ * k);
             if (st != O_OK) {
 #pragma omp critical

@@ -55,6 +55,7 @@ SIGNATURES = {
     "lbm_set_rates": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_order_rates": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_set_outlet": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double]),
+    "lbm_set_wall_distances": (ctypes.c_int, [_vp, _fp]),
     "lbm_set_inlet": (ctypes.c_int, [_vp, _fp]),
     "lbm_set_inlet_cells": (ctypes.c_int, [_vp, _fp]),
     "lbm_init_fields": (ctypes.c_int, [_vp, _fp, _fp]),
@@ -159,6 +160,11 @@ class Domain:
     def set_outlet(self, kind="zero_gradient", rho_out=1.0):
         """Outlet condition: "zero_gradient" or "pressure" (rho_out)."""
         check(lbm_set_outlet(self.h, OUTLETS[kind], float(rho_out)))
+
+    def set_wall_distances(self, q=None):
+        """Wall fraction of every link, [27, nz, ny, nx] (None: halfway)."""
+        a, p = _f32(q, 27 * self.ncells)
+        check(lbm_set_wall_distances(self.h, p))
 
     def set_inlet(self, uin):
         a, p = _f32(uin, 3 * self.ncells)

@@ -249,6 +249,9 @@ struct lbm_domain {
     uint32_t *d_wall = nullptr, *d_inlet = nullptr, *d_inlrec = nullptr;
     float *d_uin = nullptr;                // [3][n_inlet]
     float *d_iterm = nullptr;              // inlet terms, [27][64] per inlet tile
+    float2 *d_bzc = nullptr;               // curved-wall coefficients, [27][64] per wall tile
+    float *d_bzaux = nullptr;              // f*_k of the curved links, [27][64] per wall tile
+    std::vector<uint32_t> h_wall, h_inlm;  // per wall-tile lane: link mask, inlet links
     uint32_t n_inl = 0;                    // inlet tiles
     std::vector<uint64_t> inlet_cells;     // inlet cells, ascending (index = inlet ordinal)
     uint32_t *d_status = nullptr;
@@ -256,6 +259,8 @@ struct lbm_domain {
     double omega = 1.0, omega_b = 1.0;
     double omega_o[4] = {1.0, 1.0, 1.0, 1.0}; // orders 3..6
     bool high1() const { return omega_o[0] == 1.0 && omega_o[1] == 1.0 && omega_o[2] == 1.0 && omega_o[3] == 1.0; }
+    bool curved() const { return d_bzc != nullptr; }
+    int variant() const { return (high1() ? kVarH1 : 0) | (curved() ? kVarCurved : 0); }
     bool unstable = false;
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
@@ -328,6 +333,8 @@ KDomain kdomain(const lbm_domain *d)
     k.sstride = (uint32_t)(d->ntiles * 64);
     k.wall = d->d_wall;
     k.iterm = d->d_iterm;
+    k.bzc = d->d_bzc;
+    k.bzaux = d->d_bzaux;
     k.status = d->d_status;
     k.P = (uint32_t)d->P;
     k.tbytes = (uint32_t)(Q * 64 * storage_bytes(d->storage));
@@ -360,42 +367,14 @@ uint32_t step_grid(const lbm_domain *d, uint32_t phase)
     return grid8((d->ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
-template <int ST, bool H>
-hipError_t launch_step_t(const lbm_domain *d, uint32_t phase)
-{
-    const KDomain k = kdomain(d);
-    if (phase == 0)
-        hipLaunchKernelGGL((k_stream_collide<ST, H>), dim3(step_grid(d, 0)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
-                           (uint32_t)d->ntiles);
-    else
-        hipLaunchKernelGGL((k_local_collide<ST, H>), dim3(step_grid(d, 1)), dim3(kBlock), 0, d->stream, k, d->d_tiles,
-                           (uint32_t)d->ntiles);
-    return hipGetLastError();
-}
-
-hipError_t launch_step(const lbm_domain *d, uint32_t phase)
-{
-    if (d->ntiles == 0)
-        return hipSuccess;
-    const bool h1 = d->high1();
-    switch (d->storage) {
-    case LBM_FP32:
-        return h1 ? launch_step_t<ST_FP32, true>(d, phase) : launch_step_t<ST_FP32, false>(d, phase);
-    case LBM_FP16S:
-        return h1 ? launch_step_t<ST_FP16S, true>(d, phase) : launch_step_t<ST_FP16S, false>(d, phase);
-    default:
-        return h1 ? launch_step_t<ST_BF16S, true>(d, phase) : launch_step_t<ST_BF16S, false>(d, phase);
-    }
-}
-
-template <typename F> void dispatch_storage(int st, F &&f)
+template <typename F> decltype(auto) dispatch_storage(int st, F &&f)
 {
     if (st == LBM_FP32)
-        f(std::integral_constant<int, ST_FP32>{});
+        return f(std::integral_constant<int, ST_FP32>{});
     else if (st == LBM_FP16S)
-        f(std::integral_constant<int, ST_FP16S>{});
+        return f(std::integral_constant<int, ST_FP16S>{});
     else
-        f(std::integral_constant<int, ST_BF16S>{});
+        return f(std::integral_constant<int, ST_BF16S>{});
 }
 
 int sync_status(lbm_domain *d)
@@ -440,12 +419,49 @@ void free_domain(lbm_domain *d)
         dfree(s, d->d_inlrec);
         dfree(s, d->d_uin);
         dfree(s, d->d_iterm);
+        dfree(s, d->d_bzc);
+        dfree(s, d->d_bzaux);
         dfree(s, d->d_stats);
         dfree(s, d->d_status);
         if (d->own_stream)
             (void)hipStreamDestroy(s);
     }
     delete d;
+}
+
+// Calls fn(std::integral_constant<int, ST>, std::integral_constant<int, V>)
+// for a storage and a kernel variant known at run time.
+template <class Fn> decltype(auto) with_kernel(int storage, int v, Fn &&fn)
+{
+    return dispatch_storage(storage, [&](auto st) {
+        switch (v) {
+        case 0:
+            return fn(st, std::integral_constant<int, 0>{});
+        case 1:
+            return fn(st, std::integral_constant<int, 1>{});
+        case 2:
+            return fn(st, std::integral_constant<int, 2>{});
+        default:
+            return fn(st, std::integral_constant<int, 3>{});
+        }
+    });
+}
+
+hipError_t launch_step(const lbm_domain *d, uint32_t phase)
+{
+    if (d->ntiles == 0)
+        return hipSuccess;
+    const KDomain k = kdomain(d);
+    with_kernel(d->storage, d->variant(), [&](auto st, auto v) {
+        constexpr int ST = decltype(st)::value, V = decltype(v)::value;
+        if (phase == 0)
+            hipLaunchKernelGGL((k_stream_collide<ST, V>), dim3(step_grid(d, 0)), dim3(kBlock), 0, d->stream, k,
+                               d->d_tiles, (uint32_t)d->ntiles);
+        else
+            hipLaunchKernelGGL((k_local_collide<ST, V>), dim3(step_grid(d, 1)), dim3(kBlock), 0, d->stream, k,
+                               d->d_tiles, (uint32_t)d->ntiles);
+    });
+    return hipGetLastError();
 }
 
 // Rebuild the inlet terms of the inlet tiles from the inlet velocity (all
@@ -470,6 +486,20 @@ hipError_t side_refresh(const lbm_domain *d)
     const uint32_t blocks = (uint32_t)(((uint64_t)d->ny * d->nz + 255) / 256);
     dispatch_storage(d->storage, [&](auto st) {
         hipLaunchKernelGGL((k_side_refresh<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k);
+    });
+    return hipGetLastError();
+}
+
+// Curved-wall values of a phase-0 state (k_curved_refresh).
+hipError_t curved_refresh(const lbm_domain *d)
+{
+    if (!d->d_bzaux || !d->ntiles)
+        return hipSuccess;
+    const KDomain k = kdomain(d);
+    const uint32_t blocks = (uint32_t)((d->ntiles + 3) / 4);
+    dispatch_storage(d->storage, [&](auto st) {
+        hipLaunchKernelGGL((k_curved_refresh<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k,
+                           (const TileRec *)d->d_tiles, (uint32_t)d->ntiles);
     });
     return hipGetLastError();
 }
@@ -504,6 +534,7 @@ int init_eq(lbm_domain *d, const float *rho_dev, const float *u_dev)
     HIP_TRY(hipGetLastError());
     d->phase = 0;
     HIP_TRY(side_refresh(d));
+    HIP_TRY(curved_refresh(d));
     HIP_TRY(hipMemsetAsync(d->d_status, 0, sizeof(uint32_t), d->stream));
     d->unstable = false;
     return LBM_OK;
@@ -564,6 +595,11 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     d->nwall = T.wall.size() / 64;
     d->n_updated = T.n_updated;
     d->h_tiles = T.recs;
+    d->h_wall = T.wall;
+    d->h_inlm.assign(T.wall.size(), 0u);
+    for (size_t l = 0; l < T.inlet.size(); ++l)
+        if (T.inlet[l] != kNoRec)
+            d->h_inlm[l] = T.inlrec[(size_t)T.inlet[l] * kRecWords];
     d->n_inl = T.n_inl;
     d->inlet_cells = std::move(inlet_cells);
     auto bail = [&](int code) {
@@ -634,21 +670,12 @@ hipError_t add_kernel_node(hipGraph_t g, hipGraphNode_t prev, const void *func, 
     return hipGraphAddKernelNode(out, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
 }
 
-template <int ST, bool H> const void *step_kernel_t(uint32_t phase)
+const void *step_kernel(int storage, int v, uint32_t phase)
 {
-    return phase == 0 ? (const void *)k_stream_collide<ST, H> : (const void *)k_local_collide<ST, H>;
-}
-
-const void *step_kernel(int storage, bool h1, uint32_t phase)
-{
-    switch (storage) {
-    case LBM_FP32:
-        return h1 ? step_kernel_t<ST_FP32, true>(phase) : step_kernel_t<ST_FP32, false>(phase);
-    case LBM_FP16S:
-        return h1 ? step_kernel_t<ST_FP16S, true>(phase) : step_kernel_t<ST_FP16S, false>(phase);
-    default:
-        return h1 ? step_kernel_t<ST_BF16S, true>(phase) : step_kernel_t<ST_BF16S, false>(phase);
-    }
+    return with_kernel(storage, v, [&](auto st, auto vc) -> const void * {
+        constexpr int ST = decltype(st)::value, V = decltype(vc)::value;
+        return phase == 0 ? (const void *)k_stream_collide<ST, V> : (const void *)k_local_collide<ST, V>;
+    });
 }
 
 // Build (not capture) a graph of kGraphSteps chained step nodes starting in
@@ -664,7 +691,7 @@ int build_graph(lbm_domain *d)
     uint32_t nt = (uint32_t)d->ntiles;
     hipGraphNode_t prev = nullptr;
     for (int s = 0; s < kGraphSteps; ++s) {
-        const void *fn = step_kernel(d->storage, d->high1(), (uint32_t)(s & 1));
+        const void *fn = step_kernel(d->storage, d->variant(), (uint32_t)(s & 1));
         void *args[] = {&k, &tiles, &nt};
         hipGraphNode_t node = nullptr;
         hipError_t e = add_kernel_node(g, prev, fn, step_grid(d, (uint32_t)(s & 1)), kBlock, args, &node);
@@ -760,6 +787,85 @@ int lbm_set_outlet(lbm_domain *d, int kind, double rho_out)
     d->outlet_kind = kind;
     d->rho_out = rho_out;
     HIP_TRY(side_refresh(d));
+    d->graph_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_set_wall_distances(lbm_domain *d, const float *q)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    const size_t nco = (size_t)d->nwall * Q * 64;
+    std::vector<float2> coef;
+    std::vector<uint32_t> bz(d->h_tiles.size(), 0u);
+    if (q) {
+        coef.assign(nco, make_float2(1.f, 0.f));
+        for (size_t t = 0; t < d->h_tiles.size(); ++t) {
+            const TileRec &r = d->h_tiles[t];
+            if (r.wall < 0)
+                continue;
+            for (uint32_t l = 0; l < 64; ++l) {
+                if (!((r.act[l >> 5] >> (l & 31)) & 1u))
+                    continue;
+                const uint64_t c = (uint64_t)r.tile * 64 + l;
+                const size_t wl = (size_t)r.wall * 64 + l;
+                const uint32_t m = d->h_wall[wl], il = d->h_inlm[wl];
+                for (int k = 0; k < Q; ++k) {
+                    if (!((m >> k) & 1u) || ((il >> k) & 1u))
+                        continue; // not a wall link
+                    const double qq = q[(size_t)k * d->ncells + c];
+                    if (!(qq > 0.0 && qq <= 1.0))
+                        return fail(LBM_ERR_ARG, "wall fraction %g of link %d of cell %llu outside (0, 1]", qq, k,
+                                    (unsigned long long)c);
+                    double a, b;
+                    if (qq == 0.5 || (qq < 0.5 && ((m >> (Q - 1 - k)) & 1u)))
+                        continue; // halfway rule
+                    if (qq < 0.5) {
+                        a = 2.0 * qq;
+                        b = 1.0 - 2.0 * qq;
+                    } else {
+                        a = 1.0 / (2.0 * qq);
+                        b = -(1.0 - 1.0 / (2.0 * qq));
+                    }
+                    coef[((size_t)r.wall * Q + k) * 64 + l] = make_float2((float)a, (float)b);
+                    bz[t] |= 1u << k;
+                }
+            }
+        }
+    }
+    bool any = false;
+    for (uint32_t b : bz)
+        any |= b != 0;
+    HIP_TRY(normalise(d));
+    if (any && !d->d_bzc) {
+        if (dalloc(d->stream, (void **)&d->d_bzc, nco * sizeof(float2)) != hipSuccess ||
+            dalloc(d->stream, (void **)&d->d_bzaux, nco * sizeof(float)) != hipSuccess) {
+            dfree(d->stream, d->d_bzc);
+            d->d_bzc = nullptr;
+            d->d_bzaux = nullptr;
+            return fail(LBM_ERR_OOM, "curved-wall tables");
+        }
+        d->device_bytes += nco * (sizeof(float2) + sizeof(float));
+    }
+    if (!any && d->d_bzc) {
+        dfree(d->stream, d->d_bzc);
+        dfree(d->stream, d->d_bzaux);
+        d->d_bzc = nullptr;
+        d->d_bzaux = nullptr;
+        d->device_bytes -= nco * (sizeof(float2) + sizeof(float));
+    }
+    for (size_t t = 0; t < bz.size(); ++t)
+        d->h_tiles[t].bz = bz[t];
+    if (!d->h_tiles.empty())
+        HIP_TRY(copy_sync(d->stream, d->d_tiles, d->h_tiles.data(), d->h_tiles.size() * sizeof(TileRec),
+                          hipMemcpyHostToDevice));
+    if (any) {
+        HIP_TRY(copy_sync(d->stream, d->d_bzc, coef.data(), nco * sizeof(float2), hipMemcpyHostToDevice));
+        HIP_TRY(curved_refresh(d));
+        HIP_TRY(hipStreamSynchronize(d->stream));
+    }
     d->graph_dirty = true;
     return LBM_OK;
 }
@@ -972,7 +1078,7 @@ int lbm_set_populations(lbm_domain *d, const float *f)
             hipLaunchKernelGGL((k_import<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, df);
         });
         d->phase = 0;
-        if (hipGetLastError() != hipSuccess || side_refresh(d) != hipSuccess ||
+        if (hipGetLastError() != hipSuccess || side_refresh(d) != hipSuccess || curved_refresh(d) != hipSuccess ||
             hipStreamSynchronize(d->stream) != hipSuccess)
             rc = fail(LBM_ERR_DEVICE, "population import failed");
     }

@@ -43,6 +43,11 @@ enum : uint8_t { FL_FLUID = 0, FL_SOLID = 1, FL_INLET = 2, FL_OUTLET = 3 };
 // moving-wall inlet links, bit 31 the cell is not updated.
 constexpr uint32_t kMaskBB = (1u << Q) - 1;
 constexpr uint32_t kMaskOutlet = 1u << 29;
+
+// Step-kernel variants: bit 0 -- every rate of order >= 3 is 1 (the
+// reduced collision); bit 1 -- curved walls (interpolated bounce-back).
+// Domains without curved walls run kernels compiled without that code.
+constexpr int kVarH1 = 1, kVarCurved = 2, kVariants = 4;
 constexpr uint32_t kMaskInlet = 1u << 30;
 constexpr uint32_t kMaskSkip = 1u << 31;
 // inlet record of a cell with moving-wall inlet links: word 0 the link mask,
@@ -101,6 +106,8 @@ struct KDomain {
     uint32_t step0, nsteps, ph0, pad;
     uint32_t outlet;         // 0: zero-gradient outlet, 1: constant pressure rho_out / 3
     float rho_out;
+    const float2 *bzc;       // curved-wall coefficients, [27][64] per wall tile (see curved_walls)
+    float *bzaux;            // f*_k of the lanes' previous step, [27][64] per wall tile
 };
 
 // One entry of a tile list (48 bytes; a wave reads it with scalar loads).
@@ -117,7 +124,7 @@ struct TileRec {
     uint32_t edge;   // 1: an updated cell of the tile lies on the outlet plane x = nx - 1
     uint32_t bball;  // links that every updated cell of the tile bounces back
     uint32_t ord;    // position of the tile in its domain's tile list
-    uint32_t pad;
+    uint32_t bz;     // links with a curved-wall coefficient in some cell of the tile
 };
 
 // Tile-major population layout: the 27 populations of the 64 cells of a
@@ -564,6 +571,45 @@ __device__ __forceinline__ void outlet_ghost_shift(const KDomain &d, float rho, 
         g[j] = a * py[j % 3] * pz[j / 3];
 }
 
+// Curved walls (Sec. 2.2, interpolated bounce-back after Bouzidi et al.).
+// For a wall link k of cell x, at fraction q of the link towards x - c_k,
+// the linear interpolation gives f_k = 2q f*_kbar(x) + (1 - 2q) f*_kbar(x + c_k)
+// for q < 1/2 and f_k = f*_kbar(x) / (2q) + (1 - 1/(2q)) f*_k(x) for
+// q >= 1/2.  On entry f[k] holds the halfway value f*_kbar(x) and f[kbar]
+// the value pulled for kbar, which is f*_kbar(x + c_k) (the host gives the
+// halfway coefficients where kbar is no plain link).  f*_k(x) cannot be
+// read from the slots: in the streaming step the lane of x + c_k owns
+// that slot, so each step keeps it in bzaux.  The host stores per lane
+// and link (a, b): f_k <- a f_k + b f_kbar for b > 0, a f_k - b aux_k
+// otherwise; (1, 0) where the lane has no curved link k.
+__device__ __forceinline__ void curved_walls(const KDomain &d, const TileRec &rec, uint32_t lane, float (&f)[Q])
+{
+    const size_t base = (size_t)(uint32_t)rec.wall * (Q * 64u) + lane;
+    float nf[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        if ((rec.bz >> k) & 1u) {
+            const float2 c = d.bzc[base + k * 64u];
+            const float other = c.y > 0.f ? f[Q - 1 - k] : d.bzaux[base + k * 64u];
+            nf[k] = c.x * f[k] + __builtin_fabsf(c.y) * other;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+        if ((rec.bz >> k) & 1u)
+            f[k] = nf[k];
+}
+
+// Keeps f*_k of the lane's curved links for the next step.
+__device__ __forceinline__ void curved_keep(const KDomain &d, const TileRec &rec, uint32_t lane, const float (&f)[Q])
+{
+    const size_t base = (size_t)(uint32_t)rec.wall * (Q * 64u) + lane;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+        if ((rec.bz >> k) & 1u)
+            d.bzaux[base + k * 64u] = f[k];
+}
+
 // Byte offset of slot a_k of the lane whose coordinates are C: the plain
 // neighbour slot, or for a c_x = -1 link of a cell on the outlet plane of
 // an edge tile the side row named by h (0: the clamped upstream value to
@@ -584,7 +630,7 @@ __device__ __forceinline__ uint32_t slot_of(const KDomain &d, const Coords &C, i
 
 // Phase 0 -> 1.  EDGE: the tile has cells on the outlet plane (tile entry
 // `edge`); the other tiles compile without the outlet handling.
-template <int ST, bool HIGH1, bool EDGE>
+template <int ST, int V, bool EDGE>
 __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     using S = Storage<ST>;
@@ -630,12 +676,20 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
                 for (int k = 0; k < Q; ++k)
                     f[k] += inlet_term(d, rec, lane, k);
             }
+            if constexpr ((V & kVarCurved) != 0) {
+                if (rec.bz)
+                    curved_walls(d, rec, lane, f);
+            }
         }
     }
 
     float ux, uy, uz, m2[6];
-    const float rho = collide<HIGH1>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+    const float rho = collide<(V & kVarH1) != 0>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
+    if constexpr ((V & kVarCurved) != 0) {
+        if (wall && rec.bz)
+            curved_keep(d, rec, lane, f);
+    }
 
     // The slot addresses are recomputed rather than kept through the
     // collision (an opaque copy of the index stops the compiler from
@@ -689,13 +743,13 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
     }
 }
 
-template <int ST, bool HIGH1>
+template <int ST, int V>
 __device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     if (rec.edge)
-        stream_tile_t<ST, HIGH1, true>(d, rec, lane);
+        stream_tile_t<ST, V, true>(d, rec, lane);
     else
-        stream_tile_t<ST, HIGH1, false>(d, rec, lane);
+        stream_tile_t<ST, V, false>(d, rec, lane);
 }
 
 // Phase 1 -> 0, in two halves so that a wave can issue the loads of its
@@ -725,7 +779,7 @@ __device__ __forceinline__ void local_load(const KDomain &d, const TileRec &rec,
 // the central second-order Hermite moments M_ab (Sec. 2.2, Eqs. (15)-(19);
 // App. A, Eqs. (A.7)-(A.8)); sums of component c at stats[c * sstride +
 // 64 ord + lane].
-template <int ST, bool HIGH1>
+template <int ST, int V>
 __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &rec, uint32_t lane, float (&f)[Q])
 {
     using S = Storage<ST>;
@@ -735,9 +789,17 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
     const auto r = make_rsrc(d.buf, d.bufbytes);
     const uint32_t lin = rec.tile * 64u + lane;
     const uint32_t self = cell_bytes<es>(lin, d.tbytes);
+    if constexpr ((V & kVarCurved) != 0) {
+        if (rec.wall >= 0 && rec.bz)
+            curved_walls(d, rec, lane, f);
+    }
     float ux, uy, uz, m2[6];
-    const float rho = collide<HIGH1>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+    const float rho = collide<(V & kVarH1) != 0>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
+    if constexpr ((V & kVarCurved) != 0) {
+        if (rec.wall >= 0 && rec.bz)
+            curved_keep(d, rec, lane, f);
+    }
 #pragma unroll
     for (int k = 0; k < Q; ++k)
         S::store(r, self, pop_bytes<es>(Q - 1 - k), f[k], k);
@@ -766,12 +828,12 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
     }
 }
 
-template <int ST, bool HIGH1>
+template <int ST, int V>
 __device__ __forceinline__ void local_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     float f[Q];
     local_load<ST>(d, rec, lane, f);
-    local_finish<ST, HIGH1>(d, rec, lane, f);
+    local_finish<ST, V>(d, rec, lane, f);
 }
 
 // Inlet terms of the inlet tiles: for inlet link i of a cell, the moving-
@@ -817,7 +879,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) { return (
 // registers than the streaming step).  Each wave takes whole tiles, walking
 // the tile list with a stride of the grid's wave count (one pass when the
 // grid covers every tile).
-template <int ST, bool HIGH1>
+template <int ST, int V>
 __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const TileRec *__restrict__ tiles,
                                                            uint32_t ntiles)
 {
@@ -826,10 +888,10 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const Tile
     const uint32_t w0 =
         __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
     for (uint32_t t = w0; t < ntiles; t += nw)
-        stream_tile<ST, HIGH1>(d, tiles[t], lane);
+        stream_tile<ST, V>(d, tiles[t], lane);
 }
 
-template <int ST, bool HIGH1>
+template <int ST, int V>
 __global__ __launch_bounds__(kBlock) void k_local_collide(KDomain d, const TileRec *__restrict__ tiles,
                                                           uint32_t ntiles)
 {
@@ -838,7 +900,7 @@ __global__ __launch_bounds__(kBlock) void k_local_collide(KDomain d, const TileR
     const uint32_t w0 =
         __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
     for (uint32_t t = w0; t < ntiles; t += nw)
-        local_tile<ST, HIGH1>(d, tiles[t], lane);
+        local_tile<ST, V>(d, tiles[t], lane);
 }
 
 // Packed multi-domain step, one kernel per phase.  ctrl[0] / ctrl[2] =
@@ -848,7 +910,7 @@ __global__ __launch_bounds__(kBlock) void k_local_collide(KDomain d, const TileR
 // record (the host keeps the grid at least as large as the larger table);
 // each tile belongs to one domain, whose descriptor says whether it takes
 // part in this step.
-template <int ST, bool HIGH1, uint32_t PHASE>
+template <int ST, int V, uint32_t PHASE>
 __global__ __launch_bounds__(kBlock) void k_collide_batched(const KDomain *__restrict__ doms,
                                                          const TileRec *__restrict__ tiles0,
                                                          const TileRec *__restrict__ tiles1,
@@ -869,9 +931,9 @@ __global__ __launch_bounds__(kBlock) void k_collide_batched(const KDomain *__res
         if (k >= dd.nsteps || ((dd.ph0 + k) & 1u) != PHASE)
             continue;
         if (PHASE == 0u)
-            stream_tile<ST, HIGH1>(dd, rec, lane);
+            stream_tile<ST, V>(dd, rec, lane);
         else
-            local_tile<ST, HIGH1>(dd, rec, lane);
+            local_tile<ST, V>(dd, rec, lane);
     }
 }
 
@@ -968,6 +1030,30 @@ __global__ __launch_bounds__(256) void k_side_refresh(KDomain d)
 #pragma unroll
     for (int j = 0; j < 9; ++j)
         S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, f[3 * j] + g[j], 3 * j);
+}
+
+// bzaux from a phase-0 state (after an initialisation, an import or new
+// wall fractions): f*_k of each curved link, slot (x, 26 - k).  One wave
+// per tile entry.
+template <int ST>
+__global__ __launch_bounds__(256) void k_curved_refresh(KDomain d, const TileRec *__restrict__ tiles, uint32_t ntiles)
+{
+    using S = Storage<ST>;
+    constexpr uint32_t es = S::bytes;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
+    if (t >= ntiles)
+        return;
+    const TileRec rec = tiles[t];
+    if (rec.wall < 0 || !rec.bz || !lane_active(rec, lane))
+        return;
+    const auto r = make_rsrc(d.buf, d.bufbytes);
+    const uint32_t self = cell_bytes<es>(rec.tile * 64u + lane, d.tbytes);
+    float f[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+        f[k] = ((rec.bz >> k) & 1u) ? S::load(r, self, pop_bytes<es>(Q - 1 - k), k) : 0.f;
+    curved_keep(d, rec, lane, f);
 }
 
 // f = f^eq(rho, u) in product form: the sixth-order Hermite equilibrium of

@@ -175,6 +175,56 @@ class Nozzle:
         fl[:, :, -1] = np.where(inside[:, :, -1], OUTLET, SOLID)
         return fl
 
+    def radius_at(self, x: np.ndarray) -> np.ndarray:
+        """R at any axial position x (cells, x = i + 0.5 at the centre of
+        plane i); continuous except at the sudden expansion."""
+        L_in = 4 * self.R if self.inlet_len is None else self.inlet_len
+        L_th = 8 * self.R if self.throat_len is None else self.throat_len
+        L_cone = (self.R - self.r_throat) / math.tan(math.radians(self.half_angle_deg))
+        x = np.asarray(x, dtype=np.float64)
+        r = np.full(x.shape, self.R)
+        cone = (x >= L_in) & (x < L_in + L_cone)
+        r = np.where(cone, self.R - (x - L_in) * (self.R - self.r_throat) / L_cone, r)
+        throat = (x >= L_in + L_cone) & (x < L_in + L_cone + L_th)
+        return np.where(throat, self.r_throat, r)
+
+    def wall_distances(self, flags: np.ndarray | None = None, iters: int = 40) -> np.ndarray:
+        """q[27, n, n, length]: for each link i of an updated cell x whose
+        neighbour x - c_i is solid, the fraction of the link from x at
+        which it crosses the nozzle surface r = R(x) (bisection of the
+        inside/outside test along the link); 0.5 everywhere else."""
+        fl = self.flags() if flags is None else flags
+        nz_, ny_, nx_ = fl.shape
+        q = np.full((27,) + fl.shape, 0.5)
+        upd = (fl == FLUID) | (fl == OUTLET)
+        c = self.n / 2.0
+        zz, yy, xx = np.nonzero(upd)
+        for i in range(27):
+            cxi, cyi, czi = i % 3 - 1, (i // 3) % 3 - 1, i // 9 - 1
+            if cxi == cyi == czi == 0:
+                continue
+            sx, sy, sz = xx - cxi, yy - cyi, zz - czi
+            ok = (sx >= 0) & (sx < nx_) & (sy >= 0) & (sy < ny_) & (sz >= 0) & (sz < nz_)
+            sel = np.flatnonzero(ok)
+            sel = sel[fl[sz[sel], sy[sel], sx[sel]] == SOLID]
+            if sel.size == 0:
+                continue
+            px, py, pz = xx[sel] + 0.5, yy[sel] + 0.5, zz[sel] + 0.5
+
+            def outside(t):
+                ax = px - t * cxi
+                rr = np.hypot(py - t * cyi - c, pz - t * czi - c)
+                return rr >= self.radius_at(ax)
+
+            lo, hi = np.zeros(sel.size), np.ones(sel.size)
+            for _ in range(iters):
+                mid = 0.5 * (lo + hi)
+                out = outside(mid)
+                hi = np.where(out, mid, hi)
+                lo = np.where(out, lo, mid)
+            q[i, zz[sel], yy[sel], xx[sel]] = hi
+        return q
+
     def mean_inlet_velocity(self, u_throat_mean: float) -> float:
         """u0 = u_thr (d_thr / d0)^2 (Sec. 2.2, Eq. (11))."""
         return u_throat_mean * (self.r_throat / self.R) ** 2

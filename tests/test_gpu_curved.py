@@ -1,0 +1,216 @@
+"""Curved walls (interpolated bounce-back, Sec. 2.2) on the GPU against the
+oracle: random states and wall fractions on geometries with every boundary
+kind, state access after odd step counts and a change of the fractions, the
+full-size nozzle with its surface fractions at sampled cells, and packed
+execution next to a domain without curved walls."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2204_10566_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2204_10566_amd import capi
+
+    return capi
+
+
+def updated(fl):
+    return (fl == I.FLUID) | (fl == I.OUTLET)
+
+
+def random_pops(fl, seed):
+    return I.random_populations(fl.shape, seed).astype(np.float32).astype(np.float64)
+
+
+def channel(nx, ny, nz):
+    """Inlet and outlet planes, walls in y, z periodic, an obstacle, a
+    one-cell gap (walls on both sides of a link) and a solid cell on the
+    outlet plane."""
+    fl = np.zeros((nz, ny, nx), np.uint8)
+    fl[:, 0, :] = I.SOLID
+    fl[:, -1, :] = I.SOLID
+    fl[:, 1:-1, 0] = I.INLET
+    fl[:, 1:-1, -1] = I.OUTLET
+    fl[min(2, nz - 1), 3:5, nx // 3:nx // 3 + 3] = I.SOLID
+    fl[:, 2, nx // 2] = I.SOLID  # with the wall at y = 0: a gap one cell wide at y = 1
+    fl[0, ny // 2, -1] = I.SOLID
+    return fl
+
+
+def random_q(fl, seed):
+    """FP32-representable fractions in (0, 1], with exact 1/2 and 1 among
+    them; the library reads them in FP32, the oracle gets the same values."""
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(0.02, 1.0, (27,) + fl.shape)
+    pick = rng.uniform(size=q.shape)
+    q[pick < 0.1] = 0.5
+    q[pick > 0.95] = 1.0
+    return q.astype(np.float32).astype(np.float64)
+
+
+def inlet_velocity(fl, seed, amp=0.03):
+    rng = np.random.default_rng(seed)
+    uin = np.zeros((3,) + fl.shape, np.float32)
+    uin[:, fl == I.INLET] = amp * rng.uniform(-1, 1, (3, int((fl == I.INLET).sum())))
+    return uin
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+@pytest.mark.parametrize("shape,rates", [((23, 9, 5), (1 / 0.57, 1.2, 1.0)), ((128, 10, 6), (1 / 0.55, 1.1, 1.3))])
+def test_curved_walls_random_states(capi, orc, storage, shape, rates):
+    """1 and 6 steps from random populations with random wall fractions,
+    for the reduced (omega_high = 1) and the general collision."""
+    fl = channel(*shape)
+    uin = inlet_velocity(fl, 3)
+    q = random_q(fl, 7)
+    f0 = random_pops(fl, 5)
+    upd = updated(fl)
+    tol = 4e-7 if storage == "fp32" else 2e-3
+    for steps in (1, 6):
+        say(f"curved walls {shape} {storage} rates={rates} steps={steps}")
+        d = capi.Domain(fl, periodic=4, storage=storage)
+        d.set_rates(*rates)
+        d.set_wall_distances(q)
+        d.set_inlet(uin)
+        d.set_populations(f0)
+        fs = d.populations().astype(np.float64)
+        d.step(steps)
+        st, fo = orc.step(fl, fs, orc.rates_vector(*rates), steps, periodic=4, uin=uin, q=q)
+        assert st == 0
+        err = np.abs(d.populations()[:, upd] - fo[:, upd]).max()
+        say(f"  max abs err {err:.3e}")
+        assert err <= tol * steps
+        d.destroy()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_curved_walls_state_access_and_change(capi, orc, storage):
+    """3 steps, export (odd count), 2 steps, new fractions after an odd
+    count, 3 steps, fractions cleared (halfway), 2 steps, with the pressure
+    outlet on: each segment equals the oracle's pull update."""
+    fl = channel(23, 9, 5)
+    uin = inlet_velocity(fl, 21)
+    f0 = random_pops(fl, 13)
+    q1, q2 = random_q(fl, 1), random_q(fl, 2)
+    rates = (1 / 0.6, 1.1, 1.0)
+    rv = orc.rates_vector(*rates)
+    upd = updated(fl)
+    tol = 4e-7 if storage == "fp32" else 2e-3
+    say(f"curved walls state access {storage}")
+    d = capi.Domain(fl, periodic=4, storage=storage)
+    d.set_rates(*rates)
+    d.set_outlet("pressure", 1.01)
+    d.set_wall_distances(q1)
+    d.set_inlet(uin)
+    d.set_populations(f0)
+    fo = d.populations().astype(np.float64)
+    total = 0
+    cur = q1
+    for n, q in [(3, q1), (2, q1), (3, q2), (2, None)]:
+        if q is not cur:
+            d.set_wall_distances(q)
+            cur = q
+        d.step(n)
+        total += n
+        st, fo = orc.step(fl, fo, rv, n, periodic=4, uin=uin, outlet=("pressure", 1.01), q=q)
+        assert st == 0
+        err = np.abs(d.populations()[:, upd] - fo[:, upd]).max()
+        say(f"  after {total} steps: max abs err {err:.3e}")
+        assert err <= tol * total
+
+
+def test_curved_walls_full_size_nozzle_sampled(capi, orc):
+    """Full-size nozzle (96x96x768) with the wall fractions of its surface,
+    3 steps in the benchmark's launch configuration; cells next to the wall,
+    in the throat and at random against the oracle's dependency-cone run."""
+    cfg = I.nozzle_config("re500")
+    fl, tau = cfg["flags"], cfg["tau"]
+    q = cfg["nozzle"].wall_distances(fl).astype(np.float32)
+    u0 = cfg["u0"].astype(np.float32)
+    uin = cfg["uin"].astype(np.float32)
+    say(f"nozzle re500 {fl.shape} curved walls 3 steps")
+    d = capi.Domain(fl, periodic=0)
+    d.set_params(tau, 1.0 / tau, 1.0)
+    d.set_wall_distances(q)
+    d.set_inlet(uin)
+    d.init_fields(None, u0)
+    d.step(3)
+    fg = d.populations().reshape(27, -1)
+    upd = np.flatnonzero(updated(fl).ravel())
+    curved = np.flatnonzero((q.reshape(27, -1) != 0.5).any(axis=0))
+    curved = np.intersect1d(curved, upd)
+    rng = np.random.default_rng(2)
+    cells = np.unique(np.concatenate([rng.choice(curved, 200, replace=False), rng.choice(upd, 60, replace=False)]))
+    st, fo = orc.run_cells(fl, cells, orc.rates_vector(1 / tau), 3, periodic=0, uin=uin, u0=u0,
+                           q=q.astype(np.float64))
+    assert st == 0
+    err = np.abs(fg[:, cells] - fo).max()
+    say(f"  {cells.size} cells, max abs err {err:.3e}")
+    assert err <= 1e-6
+
+
+def test_curved_walls_in_batch_equal_alone(capi):
+    """A curved-wall domain packed with two halfway domains: each ends
+    exactly where it ends alone."""
+    shapes = [((23, 9, 5), 11), ((40, 12, 7), None), ((31, 10, 4), 12)]
+    steps = [17, 24, 9]
+    say("curved walls packed vs alone")
+
+    def make(k):
+        shape, qseed = shapes[k]
+        fl = channel(*shape)
+        d = capi.Domain(fl, periodic=4, storage="fp16s")
+        d.set_rates(1 / 0.6, 1 / 0.6, 1.0)
+        if qseed is not None:
+            d.set_wall_distances(random_q(fl, qseed))
+        d.set_inlet(inlet_velocity(fl, 50 + k, 0.02))
+        d.init_fields(None, None)
+        return d
+
+    alone = []
+    for k in range(3):
+        d = make(k)
+        d.step(steps[k])
+        alone.append(d.populations())
+        d.destroy()
+    doms = [make(k) for k in range(3)]
+    b = capi.Batch(1 << 32, "fp16s")
+    slots = [b.admit(d, n) for d, n in zip(doms, steps)]
+    b.step(max(steps))
+    assert sorted(b.poll(wait=True)) == sorted(slots)
+    for k, s in enumerate(slots):
+        b.release(s)
+        assert np.array_equal(doms[k].populations(), alone[k]), f"domain {k} differs"
+        doms[k].destroy()
+    b.destroy()
+
+
+def test_wall_distances_reject_bad_fractions(capi):
+    fl = channel(23, 9, 5)
+    d = capi.Domain(fl, periodic=4)
+    q = np.full((27,) + fl.shape, 0.5, np.float32)
+    i = 16  # c = (0, 1, 0): for a cell at y = 1, x - c_i is the wall row y = 0
+    q[i, 1, 1, 5] = 0.0
+    with pytest.raises(Exception):
+        d.set_wall_distances(q)
+    q[i, 1, 1, 5] = 1.5
+    with pytest.raises(Exception):
+        d.set_wall_distances(q)
+    q[i, 1, 1, 5] = 0.3
+    d.set_wall_distances(q)
+    # a fraction outside (0, 1] at a link that is not a wall link is ignored
+    q[13, 1, 4, 5] = 7.0
+    d.set_wall_distances(q)
+    d.set_wall_distances(None)
+    d.destroy()
