@@ -141,26 +141,29 @@ def serving_leg(full: bool, storage="fp16s"):
 
 
 def precision_leg(capi, torch, stream):
-    """Error of each storage format against the FP64 oracle reference
-    (tests/golden/precision_re6500_quarter.npz, written by the oracle): the
-    Re 6500 nozzle at a quarter of the 128 x 128 x 1536 size, 2000 steps;
-    then the full 128 x 128 x 1536 Re 6500 nozzle timed in each format."""
+    """Error of each storage format against the FP64 oracle references
+    (tests/golden/precision_re6500_quarter_{200,2000}.npz, written by the
+    oracle): the Re 6500 nozzle at a quarter of the 128 x 128 x 1536 size
+    after 200 and after 2000 steps; then the full 128 x 128 x 1536 Re 6500
+    nozzle timed in each format."""
     import numpy as np
 
     from paper_2204_10566_amd import inputs as I
 
     out = {}
-    ref_path = os.path.join(ROOT, "tests", "golden", "precision_re6500_quarter.npz")
-    if os.path.exists(ref_path):
+    cfg = I.nozzle_config("re6500_quarter")
+    fl = cfg["flags"]
+    upd = ((fl == 0) | (fl == 3)).ravel()
+    for steps in (200, 2000):
+        ref_path = os.path.join(ROOT, "tests", "golden", f"precision_re6500_quarter_{steps}.npz")
+        if not os.path.exists(ref_path):
+            continue
         ref = np.load(ref_path)
-        cfg = I.nozzle_config("re6500_quarter")
-        fl = cfg["flags"]
-        upd = ((fl == 0) | (fl == 3)).ravel()
         ur = ref["u"].astype(np.float64)
         rr = ref["drho"].astype(np.float64)
         res = {"workload": "128x128x1536 Re 6500 nozzle at quarter scale (32x32x384), inlet noise 1 %, "
                            f"{int(ref['steps'])} steps from plug flow, tau={float(ref['tau']):.7f}",
-               "reference": "tests/golden/precision_re6500_quarter.npz (FP64 oracle)"}
+               "reference": f"tests/golden/precision_re6500_quarter_{steps}.npz (FP64 oracle)"}
         for st in ("fp32", "fp16s", "bf16s"):
             d = capi.Domain(fl, periodic=0, storage=st, stream=stream.cuda_stream)
             d.set_params(cfg["tau"])
@@ -173,8 +176,8 @@ def precision_leg(capi, torch, stream):
             dr = rho.ravel()[upd].astype(np.float64) - 1.0
             res[st] = {"e_u": float(np.linalg.norm(ug - ur) / np.linalg.norm(ur)),
                        "e_p": float(np.linalg.norm(dr - rr) / np.linalg.norm(rr - rr.mean())), "status": int(rc)}
-            log(f"precision {st}: {res[st]}")
-        out["quarter_scale_vs_fp64"] = res
+            log(f"precision {steps} steps {st}: {res[st]}")
+        out[f"quarter_scale_vs_fp64_{steps}_steps"] = res
     cfg = I.nozzle_config("re6500")
     for k in ("uin", "u0"):
         cfg[k] = cfg[k].astype(np.float32)

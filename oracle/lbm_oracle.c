@@ -32,7 +32,8 @@
  *     expansion order n, i.e. w_i/(n! theta0^n).
  *   - Eq. (A.3) prints the Hermite polynomials without theta0; they are
  *     used in the dimensional form H_ab = c_a c_b - theta0 delta_ab etc.
- *   - "Full expansion supported by the stencil" (after Eq. (A.6)): the sum
+ *   - The expansion to the full order the stencil supports (after
+ *     Eq. (A.6)): the sum
  *     of Eq. (4) runs over every tensor component of order n <= 6 in which
  *     no axis appears more than twice; the central moments of Eq. (8) are
  *     the 27 components with each axis appearing at most twice.

@@ -347,6 +347,37 @@ def test_row_aligned_domain(capi, orc, storage):
         d.destroy()
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+@pytest.mark.parametrize("periodic", [7, 5])
+def test_row_aligned_periodic_x(capi, orc, storage, periodic):
+    """nx = 128 with x periodic: the first and last tile of each row take
+    their boundary elements across the wrap.  Solid blocks (one touching
+    x = 0 and x = nx - 1) make wall tiles at the wrap; with y closed the
+    rows at y = 0 and y = ny - 1 bounce back every y link."""
+    nz, ny, nx = 5, 7, 128
+    fl = np.zeros((nz, ny, nx), np.uint8)
+    fl[1:3, 2:4, 0:2] = I.SOLID
+    fl[2:4, 4:6, nx - 2:] = I.SOLID
+    fl[0, 3, 60:66] = I.SOLID
+    f0 = random_pops(orc, fl, 61)
+    rates = (1 / 0.59, 1.2, 1.0)
+    upd = updated(fl)
+    tol = 4e-7 if storage == "fp32" else 2e-3
+    for steps in (1, 4):
+        say(f"row-aligned periodic x {storage} periodic={periodic} steps={steps}")
+        d = capi.Domain(fl, periodic=periodic, storage=storage)
+        d.set_rates(*rates)
+        d.set_populations(f0)
+        fs = d.populations().astype(np.float64)
+        d.step(steps)
+        st, fo = orc.step(fl, fs, orc.rates_vector(*rates), steps, periodic=periodic)
+        assert st == 0
+        err = np.abs(d.populations()[:, upd] - fo[:, upd]).max()
+        say(f"  max abs err {err:.3e}")
+        assert err <= tol * steps
+        d.destroy()
+
+
 @pytest.mark.parametrize("order_rates", [(1.3, 0.8, 1.6, 0.5), (1.0, 1.0, 1.0, 1.2)])
 def test_per_order_rates(capi, orc, order_rates):
     """A separate rate for each order 3..6 of the higher central moments:
