@@ -260,7 +260,11 @@ struct lbm_domain {
     double omega_o[4] = {1.0, 1.0, 1.0, 1.0}; // orders 3..6
     bool high1() const { return omega_o[0] == 1.0 && omega_o[1] == 1.0 && omega_o[2] == 1.0 && omega_o[3] == 1.0; }
     bool curved() const { return d_bzc != nullptr; }
-    int variant() const { return (high1() ? kVarH1 : 0) | (curved() ? kVarCurved : 0); }
+    int variant() const
+    {
+        return (high1() ? kVarH1 : 0) | (curved() ? kVarCurved : 0) |
+               (outlet_kind == LBM_OUTLET_PRESSURE ? kVarPressure : 0);
+    }
     bool unstable = false;
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
@@ -441,8 +445,16 @@ template <class Fn> decltype(auto) with_kernel(int storage, int v, Fn &&fn)
             return fn(st, std::integral_constant<int, 1>{});
         case 2:
             return fn(st, std::integral_constant<int, 2>{});
-        default:
+        case 3:
             return fn(st, std::integral_constant<int, 3>{});
+        case 4:
+            return fn(st, std::integral_constant<int, 4>{});
+        case 5:
+            return fn(st, std::integral_constant<int, 5>{});
+        case 6:
+            return fn(st, std::integral_constant<int, 6>{});
+        default:
+            return fn(st, std::integral_constant<int, 7>{});
         }
     });
 }

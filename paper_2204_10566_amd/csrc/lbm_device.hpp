@@ -45,9 +45,10 @@ constexpr uint32_t kMaskBB = (1u << Q) - 1;
 constexpr uint32_t kMaskOutlet = 1u << 29;
 
 // Step-kernel variants: bit 0 -- every rate of order >= 3 is 1 (the
-// reduced collision); bit 1 -- curved walls (interpolated bounce-back).
-// Domains without curved walls run kernels compiled without that code.
-constexpr int kVarH1 = 1, kVarCurved = 2, kVariants = 4;
+// reduced collision); bit 1 -- curved walls (interpolated bounce-back);
+// bit 2 -- constant-pressure outlet.  Domains without an option run
+// kernels compiled without its code (fewer registers, more waves).
+constexpr int kVarH1 = 1, kVarCurved = 2, kVarPressure = 4, kVariants = 8;
 constexpr uint32_t kMaskInlet = 1u << 30;
 constexpr uint32_t kMaskSkip = 1u << 31;
 // inlet record of a cell with moving-wall inlet links: word 0 the link mask,
@@ -104,15 +105,15 @@ struct KDomain {
     // batched execution: the domain takes part in global steps
     // [step0, step0 + nsteps), starting in phase ph0.
     uint32_t step0, nsteps, ph0, pad;
-    uint32_t outlet;         // 0: zero-gradient outlet, 1: constant pressure rho_out / 3
+    uint32_t outlet;         // 0: zero-gradient outlet, 1: constant pressure rho_out / 3 (kernel variant kVarPressure)
     float rho_out;
     const float2 *bzc;       // curved-wall coefficients, [27][64] per wall tile (see curved_walls)
     float *bzaux;            // f*_k of the lanes' previous step, [27][64] per wall tile
 };
 
 // One entry of a tile list (48 bytes; a wave reads it with scalar loads).
-// Everything the wave needs to issue its loads is here, so none of them
-// waits for a per-cell table.
+// An interior tile needs nothing else; a wall tile adds one 32-bit link
+// mask per lane (KDomain::wall).
 struct TileRec {
     uint32_t slot;   // domain slot in a packed launch (0 otherwise)
     uint32_t tile;   // cells [64 tile, 64 tile + 64)
@@ -122,7 +123,7 @@ struct TileRec {
     uint32_t inlm;   // union of the cells' inlet links
     uint32_t act[2]; // bit l of act[l / 32]: the cell of lane l is updated
     uint32_t edge;   // 1: an updated cell of the tile lies on the outlet plane x = nx - 1
-    uint32_t bball;  // links that every updated cell of the tile bounces back
+    uint32_t bball;  // links that every updated cell of the tile bounces back (host-side bookkeeping)
     uint32_t ord;    // position of the tile in its domain's tile list
     uint32_t bz;     // links with a curved-wall coefficient in some cell of the tile
 };
@@ -650,27 +651,17 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
             for (int k = 0; k < Q; ++k)
                 f[k] = S::load(r, cell_bytes<es>(C.row[k / 3] + C.sx[k % 3], d.tbytes), pop_bytes<es>(Q - 1 - k), k);
         } else {
-            // The tile entry says which directions any cell of the tile
-            // bounces back; for those the wave loads both candidates (for
-            // the others the own load gets an offset past the end of the
-            // array, which returns 0 without a memory access; so does the
-            // neighbour load of a direction every cell bounces back), so
-            // that every load is issued before the per-cell mask arrives;
-            // the mask only selects.  Opposite directions share their
-            // weight, so one conversion serves both candidates.
+            // The per-cell mask picks each link's slot: the own slot of a
+            // bounce-back link, else a_k.  (Loading both candidates before
+            // the mask arrives and selecting afterwards measured slower: it
+            // issues twice the load instructions.)
             const uint32_t self = cell_bytes<es>(lin, d.tbytes);
             const bool edge_lane = EDGE && C.x == d.nx - 1u;
             m = d.wall[(uint32_t)rec.wall * 64u + lane];
-            uint32_t p[Q], o[Q];
 #pragma unroll
             for (int k = 0; k < Q; ++k)
-                p[k] = S::raw(r, ((rec.bball >> k) & 1u) ? d.bufbytes : slot_of<es>(d, C, k, edge_lane, 0u), 0u);
-#pragma unroll
-            for (int k = 0; k < Q; ++k)
-                o[k] = S::raw(r, ((rec.bb >> k) & 1u) ? self : d.bufbytes, pop_bytes<es>(k));
-#pragma unroll
-            for (int k = 0; k < Q; ++k)
-                f[k] = S::from_raw(((m >> k) & 1u) ? o[k] : p[k], k);
+                f[k] = S::load(r, ((m >> k) & 1u) ? self + pop_bytes<es>(k) : slot_of<es>(d, C, k, edge_lane, 0u),
+                               0u, k);
             if (rec.inlm) {
 #pragma unroll
                 for (int k = 0; k < Q; ++k)
@@ -701,8 +692,11 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
     if (edge_lane) {
         // last-plane cell: hand the clamped values to the outlet cells it
         // feeds, cell (nx - 1, y + c_y, z + c_z) for direction k = 3 j
+        // (in a packed launch the pressure variant also runs domains with the
+        // zero-gradient outlet: d.outlet decides)
+        const bool pressure = (V & kVarPressure) != 0 && d.outlet;
         float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (d.outlet)
+        if (pressure)
             outlet_ghost_shift(d, rho, ux, uy, uz, g);
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
@@ -711,7 +705,7 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
             if (plane_step(C.y, cy(k), d.ny, d.periodic & 2u, ty) && plane_step(C.z, cz(k), d.nz, d.periodic & 4u, tz)) {
                 const uint32_t t = (tz * d.ny + ty) * d.nx + d.nx - 1u;
                 if (d.flags[t] == FL_OUTLET)
-                    S::store(r, cell_bytes<es>(t, d.tbytes), pop_bytes<es>(k), d.outlet ? f[k] + g[j] : f[k], k);
+                    S::store(r, cell_bytes<es>(t, d.tbytes), pop_bytes<es>(k), pressure ? f[k] + g[j] : f[k], k);
             }
         }
     }
@@ -817,12 +811,13 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
         if (lin - q * d.nx == d.nx - 1u) {
             // last-plane cell: its c_x = -1 values for the outlet cells
             const uint32_t z = fdiv(q, d.dny), y = q - z * d.ny;
+            const bool pressure = (V & kVarPressure) != 0 && d.outlet;
             float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (d.outlet)
+            if (pressure)
                 outlet_ghost_shift(d, rho, ux, uy, uz, g);
 #pragma unroll
             for (int j = 0; j < 9; ++j)
-                S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, d.outlet ? f[3 * j] + g[j] : f[3 * j],
+                S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, pressure ? f[3 * j] + g[j] : f[3 * j],
                          3 * j);
         }
     }
