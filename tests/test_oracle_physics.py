@@ -6,7 +6,9 @@ mass and momentum are conserved to round-off.  Physical pins with a stated
 tolerance: viscous decay of a Taylor-Green vortex and of a wall-bounded shear
 wave at nu = theta0 (tau - 1/2) (Sec. 2.1, Eq. (5)); a velocity-inlet /
 zero-gradient outlet passing a uniform stream unchanged, and the inlet
-injecting exactly its prescribed mass flux (Sec. 2.2, "Simulation details").
+injecting exactly its prescribed mass flux (Sec. 2.2, "Simulation details");
+plane Poiseuille flow between halfway walls with its analytic profile and
+pressure gradient.
 The constant-pressure outlet (non-equilibrium extrapolation, Sec. 2.2): the
 mass and momentum a uniform field receives from it in one step in closed
 form, and a stream that settles at the outlet density with the inflow's
@@ -284,6 +286,41 @@ def test_pressure_outlet_sets_density_and_passes_inflow(orc):
     st, g = orc.step(fl, f, rates, 3000, periodic=6, uin=uin)
     rho, _ = orc.moments(fl, g)
     assert np.abs(rho[0, 0, 1:] - 1.0).max() < 1e-12
+
+
+def test_poiseuille_channel(orc):
+    """Plane Poiseuille flow: fluid rows y = 1..H between halfway walls (at
+    1/2 and H + 1/2), the parabola u_x = 4 U s (H - s) / H^2 (s = y - 1/2)
+    imposed by the moving-wall inlet, the constant-pressure outlet.  At
+    steady state the mid-channel profile is the parabola (max error 1.5 % of
+    U at H = 10, the halfway walls' second-order slip) and the pressure
+    gradient is the analytic dp/dx = -8 rho nu U / H^2, i.e. drho/dx =
+    -24 nu U / H^2 with nu = theta0 (tau - 1/2), within 1 %."""
+    H, nx, tau, U = 10, 40, 0.6, 0.02
+    ny = H + 2
+    fl = np.zeros((1, ny, nx), np.uint8)
+    fl[:, 0, :] = I.SOLID
+    fl[:, -1, :] = I.SOLID
+    fl[:, 1:-1, 0] = I.INLET
+    fl[:, 1:-1, -1] = I.OUTLET
+    sdist = np.arange(ny) - 0.5
+    prof = 4 * U * sdist * (H - sdist) / H ** 2
+    uin = np.zeros((3, 1, ny, nx))
+    uin[0, 0, 1:-1, 0] = prof[1:-1]
+    u0 = np.zeros((3, 1, ny, nx))
+    u0[0, 0, 1:-1, 1:] = prof[1:-1, None]
+    f = orc.init_fields(fl, None, u0)
+    st, f = orc.step(fl, f, orc.rates_vector(1 / tau, 1 / tau, 1.0), 3000, periodic=4, uin=uin,
+                     outlet=("pressure", 1.0))
+    assert st == 0
+    rho, u = orc.moments(fl, f)
+    assert np.abs(u[0, 0, 1:-1, nx // 2] - prof[1:-1]).max() < 1.5e-2 * U
+    xs = np.arange(nx // 4, 3 * nx // 4)
+    slope = np.polyfit(xs, rho[0, ny // 2, xs], 1)[0]
+    nu = THETA0 * (tau - 0.5)
+    assert abs(slope / (-24 * nu * U / H ** 2) - 1) < 1e-2
+    # away from the inlet and outlet planes the flow is parallel
+    assert np.abs(u[1:, :, :, xs]).max() < 1e-3 * U
 
 
 def off_grid_channel(H, qb, qt):
