@@ -899,20 +899,21 @@ __global__ __launch_bounds__(kBlock) void k_local_collide(KDomain d, const TileR
 }
 
 // Packed multi-domain step, one kernel per phase.  ctrl[0] / ctrl[2] =
-// number of tile records of parity class 0 / 1, ctrl[1] = global step g.
-// The domains of class g mod 2 stream at step g and the others collide
-// locally, so each kernel walks one class's table.  One wave per tile
-// record (the host keeps the grid at least as large as the larger table);
-// each tile belongs to one domain, whose descriptor says whether it takes
-// part in this step.
+// number of tile records of parity class 0 / 1; the kernel runs global
+// step g = ctrl[1] + soff (a graph of several steps gives each of its nodes
+// its offset and advances ctrl[1] once at its end).  The domains of class
+// g mod 2 stream at step g and the others collide locally, so each kernel
+// walks one class's table.  One wave per tile record (the host keeps the
+// grid at least as large as the larger table); each tile belongs to one
+// domain, whose descriptor says whether it takes part in this step.
 template <int ST, int V, uint32_t PHASE>
 __global__ __launch_bounds__(kBlock) void k_collide_batched(const KDomain *__restrict__ doms,
                                                          const TileRec *__restrict__ tiles0,
                                                          const TileRec *__restrict__ tiles1,
-                                                         const uint32_t *__restrict__ ctrl)
+                                                         const uint32_t *__restrict__ ctrl, uint32_t soff)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t g = ctrl[1];
+    const uint32_t g = ctrl[1] + soff;
     const uint32_t cls = (g & 1u) ^ PHASE;
     const TileRec *tiles = cls ? tiles1 : tiles0;
     const uint32_t ntiles = cls ? ctrl[2] : ctrl[0];
@@ -932,10 +933,10 @@ __global__ __launch_bounds__(kBlock) void k_collide_batched(const KDomain *__res
     }
 }
 
-__global__ void k_advance_step(uint32_t *ctrl)
+__global__ void k_advance_step(uint32_t *ctrl, uint32_t by)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0)
-        ctrl[1] = ctrl[1] + 1u;
+        ctrl[1] = ctrl[1] + by;
 }
 
 // ---------------------------------------------------------------------------
