@@ -300,8 +300,9 @@ int lbm_destroy(lbm_domain *d);
 const char *lbm_last_error(void);
 
 /* -------------------------------------------------------------------- */
-/* Batched execution: many independent domains advanced by one packed    */
-/* launch per time step, replayed from a captured HIP graph.            */
+/* Batched execution: many independent domains advanced together: one   */
+/* packed launch per parity class and time step, replayed from HIP       */
+/* graphs of up to 8 steps.                                              */
 /* -------------------------------------------------------------------- */
 
 /*
@@ -322,8 +323,9 @@ int lbm_batch_create(size_t hbm_budget_bytes, int storage, void *hip_stream, lbm
  */
 int lbm_batch_admit(lbm_batch *b, lbm_domain *d, int n_steps, int *slot);
 
-/* Enqueue n packed steps (asynchronous; one graph replay per step).  A
- * resident domain takes part in exactly its admitted number of steps. */
+/* Enqueue n packed steps (asynchronous; one graph replay per up to 8
+ * steps).  A resident domain takes part in exactly its admitted number of
+ * steps. */
 int lbm_batch_step(lbm_batch *b, int n);
 
 /*

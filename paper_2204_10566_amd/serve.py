@@ -4,8 +4,9 @@ Requests (nozzle-like solves of different grid sizes and step counts) arrive
 over time.  Host-side preparation (voxel flags, inlet profile, domain
 creation and upload) runs on a worker pool; the serving thread admits
 prepared domains first-come-first-served while the batch's HBM budget has
-room, advances every resident domain with one packed, graph-replayed launch
-per time step, and hands finished domains back to the pool, which copies
+room, advances every resident domain with packed, graph-replayed launches
+(one per parity class and time step), and hands finished domains back to the
+pool, which copies
 their density and velocity to the host.  A domain's state stays on the
 device from admission to completion.  The same trace can be served one solve
 at a time for comparison.
@@ -224,8 +225,8 @@ def serve_serial(trace, storage="fp16s", workers=4, keep_fields=False, realtime=
 
 
 def run_packed(specs, storage="fp16s", steps=None, budget_bytes=None):
-    """Advance independent periodic/channel domains together (one packed launch
-    per step) and one after another; returns aggregate MLUPS of both."""
+    """Advance independent periodic/channel domains together (packed launches)
+    and one after another; returns aggregate MLUPS of both."""
     import torch
 
     def build(s):

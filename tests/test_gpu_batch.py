@@ -206,15 +206,16 @@ def test_unstable_domain_is_evicted(capi):
 
 
 def test_graph_replays_match_eager_steps(capi):
-    """lbm_step(16) replays a captured 16-step graph; three replays with host
-    reads in between equal 48 single eager steps."""
-    spec = I.DomainSpec(kind="channel", nx=36, ny=18, nz=12, tau=0.57, steps=48).materialise()
+    """lbm_step(69) replays the 64-step graph once and runs 5 eager steps
+    (ending on an odd count); three such calls with host reads in between
+    equal 207 single eager steps."""
+    spec = I.DomainSpec(kind="channel", nx=36, ny=18, nz=12, tau=0.57, steps=207).materialise()
     say("graph replays vs eager steps")
     g = build(capi, spec, "fp32")
     for _ in range(3):
-        g.step(16)
+        g.step(69)
         g.moments()
     e = build(capi, spec, "fp32")
-    for _ in range(48):
+    for _ in range(207):
         e.step(1)
     assert np.array_equal(g.populations(), e.populations())

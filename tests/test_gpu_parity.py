@@ -156,18 +156,21 @@ def test_small_nozzle_run(capi, orc):
     assert e_u <= 1e-4 and e_max <= 1e-4
 
 
-@pytest.mark.parametrize("which", ["re500"])
-def test_full_size_nozzle_sampled(capi, orc, which):
-    """Full-size nozzle (96x96x768), 3 steps in the benchmark's launch
-    configuration; populations compared at sampled cells (inlet-adjacent,
-    outlet, wall-adjacent, throat, random) against the oracle's
-    dependency-cone run from the same initial fields."""
+@pytest.mark.parametrize("which,storage", [("re500", "fp32"), ("re500", "fp16s"), ("re6500", "fp32"),
+                                           ("re6500", "fp16s")])
+def test_full_size_nozzle_sampled(capi, orc, which, storage):
+    """Full-size nozzles (96x96x768 at Re 500, 128x128x1536 at Re 6500 with
+    inlet noise), 3 steps in the benchmark's launch configuration;
+    populations compared at sampled cells (inlet-adjacent, outlet,
+    wall-adjacent, throat, random) against the oracle's dependency-cone run
+    from the same initial fields.  FP16-shifted storage rounds the state to
+    about 3e-5 absolute per step."""
     cfg = I.nozzle_config(which)
     fl, tau = cfg["flags"], cfg["tau"]
     u0 = cfg["u0"].astype(np.float32)
     uin = cfg["uin"].astype(np.float32)
-    say(f"nozzle {which} {fl.shape} 3 steps")
-    d = run_gpu(capi, fl, 0, 3, tau=tau, u0=u0, uin=uin)
+    say(f"nozzle {which} {fl.shape} {storage} 3 steps")
+    d = run_gpu(capi, fl, 0, 3, tau=tau, u0=u0, uin=uin, storage=storage)
     fg = d.populations().reshape(27, -1)
     upd = np.flatnonzero(updated(fl).ravel())
     nz_, ny_, nx_ = fl.shape
@@ -182,8 +185,9 @@ def test_full_size_nozzle_sampled(capi, orc, which):
     st, fo = orc.run_cells(fl, cells, orc.rates_vector(1 / tau), 3, periodic=0, uin=uin, u0=u0)
     assert st == 0
     err = np.abs(fg[:, cells] - fo).max()
-    say(f"nozzle {which}: {cells.size} cells, max abs err {err:.3e}")
-    assert err <= 1e-6
+    say(f"nozzle {which} {storage}: {cells.size} cells, max abs err {err:.3e}")
+    assert err <= (1e-6 if storage == "fp32" else 2e-4)
+    d.destroy()
 
 
 def test_fp16_shifted_tgv32(capi, orc):
