@@ -163,8 +163,9 @@ def test_full_size_nozzle_sampled(capi, orc, which, storage):
     inlet noise), 3 steps in the benchmark's launch configuration;
     populations compared at sampled cells (inlet-adjacent, outlet,
     wall-adjacent, throat, random) against the oracle's dependency-cone run
-    from the same initial fields.  FP16-shifted storage rounds the state to
-    about 3e-5 absolute per step."""
+    from the same initial fields.  FP16-shifted storage rounds each stored
+    value to 2^-11 of 2^14 (f - w), a few 1e-6 on these states (measured
+    2.4e-6 after 3 steps); the bound is 2e-5."""
     cfg = I.nozzle_config(which)
     fl, tau = cfg["flags"], cfg["tau"]
     u0 = cfg["u0"].astype(np.float32)
@@ -186,7 +187,7 @@ def test_full_size_nozzle_sampled(capi, orc, which, storage):
     assert st == 0
     err = np.abs(fg[:, cells] - fo).max()
     say(f"nozzle {which} {storage}: {cells.size} cells, max abs err {err:.3e}")
-    assert err <= (1e-6 if storage == "fp32" else 2e-4)
+    assert err <= (1e-6 if storage == "fp32" else 2e-5)
     d.destroy()
 
 
