@@ -267,7 +267,7 @@ def main():
     ap.add_argument("--no-stability", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path: "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path: "
               "the single-domain update runs on one MI355X and independent requests would be sharded per GPU.",
               file=sys.stderr)
         sys.exit(2)
