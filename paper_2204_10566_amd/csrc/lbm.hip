@@ -340,6 +340,8 @@ KDomain kdomain(const lbm_domain *d)
     k.iterm = d->d_iterm;
     k.bzc = d->d_bzc;
     k.bzaux = d->d_bzaux;
+    k.rowtiles = d->nx % 64 == 0 ? (uint32_t)(d->nx / 64) : 0u;
+    k.drow = make_fastdiv(k.rowtiles ? k.rowtiles : 1u);
     k.status = d->d_status;
     k.P = (uint32_t)d->P;
     k.tbytes = (uint32_t)(Q * 64 * storage_bytes(d->storage));
@@ -467,8 +469,11 @@ hipError_t launch_step(const lbm_domain *d, uint32_t phase)
     const KDomain k = kdomain(d);
     with_kernel(d->storage, d->variant(), [&](auto st, auto v) {
         constexpr int ST = decltype(st)::value, V = decltype(v)::value;
-        if (phase == 0)
-            hipLaunchKernelGGL((k_stream_collide<ST, V>), dim3(step_grid(d, 0)), dim3(kBlock), 0, d->stream, k,
+        if (phase == 0 && k.rowtiles)
+            hipLaunchKernelGGL((k_stream_collide<ST, V, true>), dim3(step_grid(d, 0)), dim3(kBlock), 0, d->stream, k,
+                               d->d_tiles, (uint32_t)d->ntiles);
+        else if (phase == 0)
+            hipLaunchKernelGGL((k_stream_collide<ST, V, false>), dim3(step_grid(d, 0)), dim3(kBlock), 0, d->stream, k,
                                d->d_tiles, (uint32_t)d->ntiles);
         else
             hipLaunchKernelGGL((k_local_collide<ST, V>), dim3(step_grid(d, 1)), dim3(kBlock), 0, d->stream, k,
@@ -683,11 +688,13 @@ hipError_t add_kernel_node(hipGraph_t g, hipGraphNode_t prev, const void *func, 
     return hipGraphAddKernelNode(out, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
 }
 
-const void *step_kernel(int storage, int v, uint32_t phase)
+const void *step_kernel(int storage, int v, uint32_t phase, bool rows)
 {
     return with_kernel(storage, v, [&](auto st, auto vc) -> const void * {
         constexpr int ST = decltype(st)::value, V = decltype(vc)::value;
-        return phase == 0 ? (const void *)k_stream_collide<ST, V> : (const void *)k_local_collide<ST, V>;
+        if (phase == 1)
+            return (const void *)k_local_collide<ST, V>;
+        return rows ? (const void *)k_stream_collide<ST, V, true> : (const void *)k_stream_collide<ST, V, false>;
     });
 }
 
@@ -704,7 +711,7 @@ int build_graph(lbm_domain *d)
     uint32_t nt = (uint32_t)d->ntiles;
     hipGraphNode_t prev = nullptr;
     for (int s = 0; s < kGraphSteps; ++s) {
-        const void *fn = step_kernel(d->storage, d->variant(), (uint32_t)(s & 1));
+        const void *fn = step_kernel(d->storage, d->variant(), (uint32_t)(s & 1), k.rowtiles != 0);
         void *args[] = {&k, &tiles, &nt};
         hipGraphNode_t node = nullptr;
         hipError_t e = add_kernel_node(g, prev, fn, step_grid(d, (uint32_t)(s & 1)), kBlock, args, &node);

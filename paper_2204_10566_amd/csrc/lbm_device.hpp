@@ -109,6 +109,8 @@ struct KDomain {
     float rho_out;
     const float2 *bzc;       // curved-wall coefficients, [27][64] per wall tile (see curved_walls)
     float *bzaux;            // f*_k of the lanes' previous step, [27][64] per wall tile
+    uint32_t rowtiles;       // nx / 64 when nx is a multiple of 64 (stream_tile_rows), else 0
+    FastDiv drow;            // division by rowtiles
 };
 
 // One entry of a tile list (48 bytes; a wave reads it with scalar loads).
@@ -737,13 +739,164 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
     }
 }
 
+// Row-aligned domains (nx a multiple of 64, KDomain::rowtiles = nx / 64):
+// a tile lies in one row, so the first cell of each of the nine source rows
+// (y - c_y, z - c_z) is the start of a tile, the same for every lane.  The
+// byte offset of slot a_k then splits into that row's tile offset and the
+// slot's offset, both wave-uniform (the buffer instruction's scalar offset),
+// plus the lane's offset of cell x - c_x within its row, one of three
+// per-lane values.  This drops the per-lane coordinate decode and address
+// arithmetic of stream_tile_t.  On the outlet plane (EDGE) the only cell of
+// a tile is its lane 63, and the side-row elements it uses and the outlet
+// cells it feeds have wave-uniform addresses too.
+struct RowAddr {
+    uint32_t y, z, j; // the tile's row and its position in the row
+    uint32_t xo[3];   // by c_x + 1: byte offset of cell (x - c_x) from the start of its row
+    uint32_t sy[3], sz[3];
+    uint32_t row[9];  // by (c_y + 1) + 3 (c_z + 1): byte offset of the first tile of the source row
+};
+
+template <uint32_t ES>
+__device__ __forceinline__ RowAddr row_addr(const KDomain &d, const TileRec &rec, uint32_t lane)
+{
+    RowAddr A;
+    const uint32_t R = d.rowtiles, q = fdiv(rec.tile, d.drow);
+    A.j = rec.tile - q * R;
+    A.z = fdiv(q, d.dny);
+    A.y = q - A.z * d.ny;
+    const uint32_t x = A.j * 64u + lane, y = A.y, z = A.z;
+    const bool px = d.periodic & 1u, py = d.periodic & 2u, pz = d.periodic & 4u;
+    // a source outside a non-periodic box belongs to a bounce-back link (the
+    // mask selects the own slot) or to the outlet (side rows); it is
+    // clamped to stay in the array
+    const uint32_t sx[3] = {x + 1u < d.nx ? x + 1u : (px ? 0u : x), x, x > 0u ? x - 1u : (px ? d.nx - 1u : 0u)};
+    A.sy[0] = y + 1u < d.ny ? y + 1u : (py ? 0u : y);
+    A.sy[1] = y;
+    A.sy[2] = y > 0u ? y - 1u : (py ? d.ny - 1u : 0u);
+    A.sz[0] = z + 1u < d.nz ? z + 1u : (pz ? 0u : z);
+    A.sz[1] = z;
+    A.sz[2] = z > 0u ? z - 1u : (pz ? d.nz - 1u : 0u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        A.xo[a] = (sx[a] >> 6) * d.tbytes + (sx[a] & 63u) * ES;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            A.row[b + 3 * c] = (A.sz[c] * d.ny + A.sy[b]) * R * d.tbytes;
+    return A;
+}
+
+// Phase 0 -> 1 for a tile of a row-aligned domain: stream_tile_t with the
+// addressing above.  EDGE: the tile holds a cell of the outlet plane.
+template <int ST, int V, bool EDGE>
+__device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec &rec, uint32_t lane)
+{
+    using S = Storage<ST>;
+    constexpr uint32_t es = S::bytes;
+    const auto r = make_rsrc(d.buf, d.bufbytes);
+    const bool wall = rec.wall >= 0;
+    if (wall && !lane_active(rec, lane))
+        return;
+    const uint32_t self = rec.tile * d.tbytes + lane * es;
+    // the outlet-plane cell: lane 63 of the last tile of its row
+    const bool edge_lane = EDGE && lane == 63u && rec.tile - fdiv(rec.tile, d.drow) * d.rowtiles == d.rowtiles - 1u;
+
+    float f[Q];
+    uint32_t m = 0;
+    {
+        const RowAddr A = row_addr<es>(d, rec, lane);
+        if (!wall) {
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+                f[k] = S::load(r, A.xo[k % 3], A.row[k / 3] + pop_bytes<es>(Q - 1 - k), k);
+        } else {
+            m = d.wall[(uint32_t)rec.wall * 64u + lane];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                uint32_t off = A.xo[k % 3] + A.row[k / 3] + pop_bytes<es>(Q - 1 - k);
+                if (EDGE && k % 3 == 0) // the clamped upstream value of an outlet cell
+                    off = edge_lane ? side_bytes<es>(d, 0u, (uint32_t)k / 3u, A.sy[(k / 3) % 3], A.sz[k / 9]) : off;
+                f[k] = S::load(r, ((m >> k) & 1u) ? self + pop_bytes<es>(k) : off, 0u, k);
+            }
+            if (rec.inlm) {
+#pragma unroll
+                for (int k = 0; k < Q; ++k)
+                    f[k] += inlet_term(d, rec, lane, k);
+            }
+            if constexpr ((V & kVarCurved) != 0) {
+                if (rec.bz)
+                    curved_walls(d, rec, lane, f);
+            }
+        }
+    }
+
+    float ux, uy, uz, m2[6];
+    const float rho = collide<(V & kVarH1) != 0>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+    check_state(d, rho, ux, uy, uz);
+    if constexpr ((V & kVarCurved) != 0) {
+        if (wall && rec.bz)
+            curved_keep(d, rec, lane, f);
+    }
+    // the lane offsets are recomputed after the collision (an opaque copy of
+    // the lane index keeps the compiler from holding them through it)
+    uint32_t lane2 = lane;
+    asm volatile("" : "+v"(lane2) : "v"(f[0]), "v"(f[13]), "v"(f[26]));
+    const RowAddr A = row_addr<es>(d, rec, lane2);
+    if constexpr (EDGE) {
+        // the outlet-plane cell hands the clamped values to the outlet cells
+        // it feeds, cell (nx - 1, y + c_y, z + c_z) for direction k = 3 j
+        // (in a packed launch the pressure variant also runs domains with
+        // the zero-gradient outlet: d.outlet decides)
+        const bool pressure = (V & kVarPressure) != 0 && d.outlet;
+        float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (pressure)
+            outlet_ghost_shift(d, rho, ux, uy, uz, g);
+#pragma unroll
+        for (int jj = 0; jj < 9; ++jj) {
+            const int k = 3 * jj;
+            uint32_t ty, tz;
+            if (plane_step(A.y, cy(k), d.ny, d.periodic & 2u, ty) && plane_step(A.z, cz(k), d.nz, d.periodic & 4u, tz)) {
+                const uint32_t t = (tz * d.ny + ty) * d.nx + d.nx - 1u;
+                if (d.flags[t] == FL_OUTLET && edge_lane)
+                    S::store(r, cell_bytes<es>(t, d.tbytes), pop_bytes<es>(k), pressure ? f[k] + g[jj] : f[k], k);
+            }
+        }
+    }
+    if (rec.inlm) {
+        // bounce-back slots of inlet links carry the term into the next step
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            f[Q - 1 - k] += inlet_term(d, rec, lane, k);
+    }
+    const uint32_t self2 = rec.tile * d.tbytes + lane2 * es;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        if (!wall) {
+            S::store(r, A.xo[k % 3], A.row[k / 3] + pop_bytes<es>(Q - 1 - k), f[Q - 1 - k], k);
+        } else {
+            uint32_t off = A.xo[k % 3] + A.row[k / 3] + pop_bytes<es>(Q - 1 - k);
+            if (EDGE && k % 3 == 0) // an outlet cell parks its leaving value
+                off = edge_lane ? side_bytes<es>(d, 1u, 8u - (uint32_t)k / 3u, A.y, A.z) : off;
+            S::store(r, ((m >> k) & 1u) ? self2 + pop_bytes<es>(k) : off, 0u, f[Q - 1 - k], k);
+        }
+    }
+}
+
 template <int ST, int V>
 __device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
-    if (rec.edge)
-        stream_tile_t<ST, V, true>(d, rec, lane);
-    else
-        stream_tile_t<ST, V, false>(d, rec, lane);
+    if (d.rowtiles) {
+        if (rec.edge)
+            stream_tile_rows<ST, V, true>(d, rec, lane);
+        else
+            stream_tile_rows<ST, V, false>(d, rec, lane);
+    } else {
+        if (rec.edge)
+            stream_tile_t<ST, V, true>(d, rec, lane);
+        else
+            stream_tile_t<ST, V, false>(d, rec, lane);
+    }
 }
 
 // Phase 1 -> 0, in two halves so that a wave can issue the loads of its
@@ -874,7 +1027,10 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) { return (
 // registers than the streaming step).  Each wave takes whole tiles, walking
 // the tile list with a stride of the grid's wave count (one pass when the
 // grid covers every tile).
-template <int ST, int V>
+// Streaming step of a single domain; ROWS: the domain is row-aligned
+// (stream_tile_rows), chosen per domain on the host, so that each kernel
+// carries only one addressing scheme.
+template <int ST, int V, bool ROWS>
 __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const TileRec *__restrict__ tiles,
                                                            uint32_t ntiles)
 {
@@ -882,8 +1038,20 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const Tile
     const uint32_t nw = gridDim.x * kWavesPerBlock;
     const uint32_t w0 =
         __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
-    for (uint32_t t = w0; t < ntiles; t += nw)
-        stream_tile<ST, V>(d, tiles[t], lane);
+    for (uint32_t t = w0; t < ntiles; t += nw) {
+        const TileRec rec = tiles[t];
+        if constexpr (ROWS) {
+            if (rec.edge)
+                stream_tile_rows<ST, V, true>(d, rec, lane);
+            else
+                stream_tile_rows<ST, V, false>(d, rec, lane);
+        } else {
+            if (rec.edge)
+                stream_tile_t<ST, V, true>(d, rec, lane);
+            else
+                stream_tile_t<ST, V, false>(d, rec, lane);
+        }
+    }
 }
 
 template <int ST, int V>
