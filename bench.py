@@ -191,6 +191,47 @@ def precision_leg(capi, torch, stream):
     return out
 
 
+def roofline_probe_leg(capi, torch, stream, n=320, steps=192):
+    """Periodic Taylor-Green vortex on n^3 cells: no walls, every cell
+    updated, n a multiple of 64 so that rows align with tiles.  At n = 320
+    one FP32 step moves 7.1 GB, far beyond the 256 MB Infinity Cache, so this
+    is a bandwidth point that the cache does not flatter; FP32 and FP16S,
+    beside a plain copy of the same byte count."""
+    import numpy as np
+
+    from paper_2204_10566_amd import inputs as I
+
+    fl = I.periodic_box(n)
+    u0 = I.taylor_green_velocity(n, n, n, 0.05).astype(np.float32)
+    out = {"workload": f"periodic Taylor-Green vortex {n}^3, u0 = 0.05, tau = 0.6, {steps} timed steps"}
+    for st in ("fp32", "fp16s"):
+        d = capi.Domain(fl, periodic=7, storage=st, stream=stream.cuda_stream)
+        d.set_params(0.6)
+        d.init_fields(None, u0)
+        info = d.info()
+        d.step(64)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        rc = d.step_status(steps)
+        e1.record(stream)
+        e1.synchronize()
+        d.destroy()
+        us = e0.elapsed_time(e1) / steps * 1e3
+        gbs = info.n_updated * info.bytes_per_cell_update / (us * 1e-6) / 1e9
+        out[st] = {"us_per_step": round(us, 2), "mlups": round(info.n_updated / us, 1),
+                   "achieved_gbs": round(gbs, 1), "frac_of_peak": round(gbs / PEAK_HBM_GBS, 4), "status": int(rc)}
+        log(f"tgv {n}^3 {st}: {out[st]}")
+    del u0
+    copy = copy_ceiling(torch, stream, fl.size * 216, reps=10)
+    out["copy_ceiling_gbs"] = copy["gbs"]
+    out["fp32_frac_of_copy"] = round(out["fp32"]["achieved_gbs"] / copy["gbs"], 4)
+    out["ratio_fp16s_vs_fp32"] = round(out["fp16s"]["mlups"] / out["fp32"]["mlups"], 3)
+    log(f"tgv {n}^3 plain copy of {copy['bytes_per_copy'] / 1e9:.1f} GB: {copy['gbs']:.0f} GB/s")
+    return out
+
+
 def stability_leg(capi, stream):
     """Stability envelope at tau -> 1/2: a 64^3 periodic double shear layer
     (u0 = 0.1, FP32) run 2000 steps at decreasing tau - 1/2 for several
@@ -265,6 +306,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-stability", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path: "
@@ -354,6 +396,9 @@ def main():
     if not args.no_precision:
         log("precision: storage formats against the FP64 reference; re6500 full-size speed")
         out["precision"] = precision_leg(capi, torch, stream)
+    if not args.no_probe:
+        log("roofline probe: periodic TGV 320^3")
+        out["roofline_probe"] = roofline_probe_leg(capi, torch, stream)
     if not args.no_stability:
         log("stability envelope (double shear layer)")
         out["stability"] = stability_leg(capi, stream)
