@@ -7,11 +7,10 @@
  * the update of Sec. 2.1, Eq. (6), with the central Hermite moments of
  * Eqs. (7)-(8), the full (sixth-order) Hermite equilibrium of Eq. (4) and
  * App. A, Eqs. (A.4)-(A.6), relaxation rates as stated after Eq. (8) and in
- * App. A, on the D3Q27 stencil of App. A, Eqs. (A.1)-(A.2); halfway
- * bounce-back walls (halfway, or interpolated for curved walls), a
- * moving-wall velocity inlet (profile of Sec. 2.2,
- * Eq. (12)) and a zero-gradient or constant-pressure (non-equilibrium
- * extrapolation, Sec. 2.2) outlet.  Each step gives exactly the pull
+ * App. A, on the D3Q27 stencil of App. A, Eqs. (A.1)-(A.2); bounce-back
+ * walls (halfway, or interpolated for curved walls), a moving-wall velocity
+ * inlet (profile of Sec. 2.2, Eq. (12)) and a zero-gradient or
+ * constant-pressure (non-equilibrium extrapolation, Sec. 2.2) outlet.  Each step gives exactly the pull
  * update (every cell gathers f_i from x - c_i, then collides); the library
  * runs it in place on a single population array, alternating a streaming
  * step and a local step so that every step reads and writes the same slots.
@@ -119,7 +118,8 @@ typedef struct lbm_domain_info {
  *   hip_stream   hipStream_t to issue work on, or NULL for a stream the
  *                library creates.  The stream must outlive the domain.
  * Allocates the population array and initialises f = f^eq(1, 0).
- * A domain needs lbm_array_bytes(...) < 4 GiB - 64 KiB.
+ * A domain needs lbm_array_bytes(...) <= 4 GiB - 64 KiB (the kernels
+ * address the array with 32-bit byte offsets).
  * Errors: LBM_ERR_ARG (bad sizes, flags or storage), LBM_ERR_OOM,
  * LBM_ERR_DEVICE.
  */
@@ -235,7 +235,9 @@ int lbm_init_fields(lbm_domain *d, const float *rho, const float *u);
  * Advance n >= 0 time steps (each: pull streaming with the boundary rules,
  * then the CHM-MRT collision of Eq. (6), fused in one kernel per step).
  * Synchronous.  Returns LBM_ERR_UNSTABLE if any step produced rho <= 0 or
- * a non-finite value; the error is sticky until lbm_init_fields.
+ * a non-finite value; the error is sticky until lbm_init_fields.  Errors:
+ * LBM_ERR_ARG for n < 0, LBM_ERR_STATE for a domain resident in a batch,
+ * LBM_ERR_DEVICE.
  */
 int lbm_step(lbm_domain *d, int n);
 
@@ -292,7 +294,7 @@ int lbm_stats_get(lbm_domain *d, float *mean_u, float *mean_uu, float *mean_sigm
 
 int lbm_domain_get_info(const lbm_domain *d, lbm_domain_info *info);
 
-/* Free the domain's device memory and its captured graphs.  A domain
+/* Free the domain's device memory and its step graphs.  A domain
  * resident in a batch must be released from it first (LBM_ERR_STATE). */
 int lbm_destroy(lbm_domain *d);
 

@@ -1,11 +1,12 @@
 // lbm.hip -- host side of the C ABI declared in include/lbm.h.
 //
-// A domain holds two population buffers (pull scheme: read one, write the
-// other, swap), the list of 64-cell tiles that contain updated cells, and
-// for tiles that touch a wall, inlet, box face or non-updated cell a 32-bit
-// link mask per cell.  Interior tiles (every cell updated, every link a
-// plain pull after periodic wrap) carry no mask and take the kernel's fast
-// path.  Steps are replayed from a captured HIP graph.
+// A domain holds one population array, updated in place by two alternating
+// kernels (streaming step and local step), the list of 64-cell tiles that
+// contain updated cells, and for tiles that touch a wall, inlet, box face or
+// non-updated cell a 32-bit link mask per cell.  Interior tiles (every cell
+// updated, every link a plain pull after periodic wrap) carry no mask and
+// take the kernels' branch-free path.  Runs of steps are replayed from HIP
+// graphs built node by node.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -141,7 +142,7 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
         uint64_t src[Q];
         for (uint64_t t = t0; t < t1; ++t) {
             bool any = false, plain = true;
-            TileRec r{0u, (uint32_t)t, -1, 0u, kNoRec, 0u, {0u, 0u}, 0u, kMaskBB, 0u, 0u};
+            TileRec r{0u, (uint32_t)t, -1, kNoRec, 0u, {0u, 0u}, 0u, 0u, 0u};
             for (int l = 0; l < 64; ++l) {
                 const uint64_t c = t * 64 + l;
                 rec[l] = kNoRec;
@@ -166,8 +167,6 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
                     any = true;
                     T.n_updated++;
                     r.act[l >> 5] |= 1u << (l & 31);
-                    r.bb |= wl[l] & kMaskBB;
-                    r.bball &= wl[l];
                     r.inlm |= il[l];
                     if (outlets && !(per & 1u) && (c % nx) == (uint64_t)nx - 1)
                         r.edge = 1u;
@@ -368,9 +367,8 @@ uint32_t grid8(uint64_t blocks) { return (uint32_t)((blocks + 7) / 8 * 8); }
 // Grid of the single-domain kernels: one wave per tile (a wave's loads and
 // collision do not overlap within the wave, and tiles per wave beyond one
 // measured slower).
-uint32_t step_grid(const lbm_domain *d, uint32_t phase)
+uint32_t step_grid(const lbm_domain *d)
 {
-    (void)phase;
     return grid8((d->ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
@@ -470,13 +468,13 @@ hipError_t launch_step(const lbm_domain *d, uint32_t phase)
     with_kernel(d->storage, d->variant(), [&](auto st, auto v) {
         constexpr int ST = decltype(st)::value, V = decltype(v)::value;
         if (phase == 0 && k.rowtiles)
-            hipLaunchKernelGGL((k_stream_collide<ST, V, true>), dim3(step_grid(d, 0)), dim3(kBlock), 0, d->stream, k,
+            hipLaunchKernelGGL((k_stream_collide<ST, V, true>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k,
                                d->d_tiles, (uint32_t)d->ntiles);
         else if (phase == 0)
-            hipLaunchKernelGGL((k_stream_collide<ST, V, false>), dim3(step_grid(d, 0)), dim3(kBlock), 0, d->stream, k,
+            hipLaunchKernelGGL((k_stream_collide<ST, V, false>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k,
                                d->d_tiles, (uint32_t)d->ntiles);
         else
-            hipLaunchKernelGGL((k_local_collide<ST, V>), dim3(step_grid(d, 1)), dim3(kBlock), 0, d->stream, k,
+            hipLaunchKernelGGL((k_local_collide<ST, V>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k,
                                d->d_tiles, (uint32_t)d->ntiles);
     });
     return hipGetLastError();
@@ -578,8 +576,8 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     const uint64_t ncells = (uint64_t)nx * ny * nz;
     const uint64_t P = plane_stride(ncells);
     const uint64_t bufbytes = array_bytes(P, ny, nz, storage);
-    // buffer offsets are 32-bit; keep room for the out-of-range offsets of
-    // skipped loads
+    // buffer instructions take 32-bit byte offsets: every slot and side-row
+    // element must be addressable by one
     if (bufbytes > (1ull << 32) - (1ull << 16))
         return fail(LBM_ERR_ARG, "domain of %llu cells needs %llu bytes of populations; the limit is 4 GiB",
                     (unsigned long long)ncells, (unsigned long long)bufbytes);
@@ -714,7 +712,7 @@ int build_graph(lbm_domain *d)
         const void *fn = step_kernel(d->storage, d->variant(), (uint32_t)(s & 1), k.rowtiles != 0);
         void *args[] = {&k, &tiles, &nt};
         hipGraphNode_t node = nullptr;
-        hipError_t e = add_kernel_node(g, prev, fn, step_grid(d, (uint32_t)(s & 1)), kBlock, args, &node);
+        hipError_t e = add_kernel_node(g, prev, fn, step_grid(d), kBlock, args, &node);
         if (e != hipSuccess) {
             (void)hipGraphDestroy(g);
             return fail(LBM_ERR_DEVICE, "graph node: %s", hipGetErrorString(e));

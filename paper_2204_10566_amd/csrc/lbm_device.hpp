@@ -22,8 +22,8 @@ constexpr float kFp16InvScale = 1.0f / 16384.0f;
 
 enum : int { ST_FP32 = 0, ST_FP16S = 1, ST_BF16S = 2 };
 
-// Launch shape and cache policy of the stream-collide kernels (tuned on
-// MI355X; see the profiles).  Cache-policy bits of buffer instructions on
+// Launch shape and cache policy of the stream-collide kernels (tuned by
+// measurement on MI355X).  Cache-policy bits of buffer instructions on
 // gfx950: 1 sc0, 2 nt, 16 sc1.
 #ifndef LBM_WAVES_PER_BLOCK
 #define LBM_WAVES_PER_BLOCK 4
@@ -38,19 +38,18 @@ constexpr uint32_t kWavesPerBlock = LBM_WAVES_PER_BLOCK;
 constexpr uint32_t kBlock = 64 * kWavesPerBlock;
 enum : uint8_t { FL_FLUID = 0, FL_SOLID = 1, FL_INLET = 2, FL_OUTLET = 3 };
 
-// wall-tile link mask of a cell: bits 0..26 halfway bounce-back for
+// wall-tile link mask of a cell: bit i (0..26) halfway bounce-back for
 // direction i, bit 29 the cell is an outlet cell, bit 30 the cell has
 // moving-wall inlet links, bit 31 the cell is not updated.
-constexpr uint32_t kMaskBB = (1u << Q) - 1;
 constexpr uint32_t kMaskOutlet = 1u << 29;
+constexpr uint32_t kMaskInlet = 1u << 30;
+constexpr uint32_t kMaskSkip = 1u << 31;
 
 // Step-kernel variants: bit 0 -- every rate of order >= 3 is 1 (the
 // reduced collision); bit 1 -- curved walls (interpolated bounce-back);
 // bit 2 -- constant-pressure outlet.  Domains without an option run
 // kernels compiled without its code (fewer registers, more waves).
 constexpr int kVarH1 = 1, kVarCurved = 2, kVarPressure = 4, kVariants = 8;
-constexpr uint32_t kMaskInlet = 1u << 30;
-constexpr uint32_t kMaskSkip = 1u << 31;
 // inlet record of a cell with moving-wall inlet links: word 0 the link mask,
 // word 1 + i the ordinal of the inlet cell that link i comes from
 constexpr uint32_t kRecWords = 28;
@@ -113,22 +112,21 @@ struct KDomain {
     FastDiv drow;            // division by rowtiles
 };
 
-// One entry of a tile list (48 bytes; a wave reads it with scalar loads).
+// One entry of a tile list (40 bytes; a wave reads it with scalar loads).
 // An interior tile needs nothing else; a wall tile adds one 32-bit link
 // mask per lane (KDomain::wall).
 struct TileRec {
     uint32_t slot;   // domain slot in a packed launch (0 otherwise)
     uint32_t tile;   // cells [64 tile, 64 tile + 64)
     int32_t wall;    // wall-tile slot (per-cell link masks), -1 for an interior tile
-    uint32_t bb;     // union of the cells' bounce-back links
     uint32_t inl;    // inlet-term block, kNoRec if no cell has an inlet link
     uint32_t inlm;   // union of the cells' inlet links
     uint32_t act[2]; // bit l of act[l / 32]: the cell of lane l is updated
     uint32_t edge;   // 1: an updated cell of the tile lies on the outlet plane x = nx - 1
-    uint32_t bball;  // links that every updated cell of the tile bounces back (host-side bookkeeping)
     uint32_t ord;    // position of the tile in its domain's tile list
     uint32_t bz;     // links with a curved-wall coefficient in some cell of the tile
 };
+static_assert(sizeof(TileRec) == 40, "tile record layout");
 
 // Tile-major population layout: the 27 populations of the 64 cells of a
 // tile are one contiguous block, population i of the cell in lane l at
