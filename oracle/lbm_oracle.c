@@ -43,11 +43,14 @@
  *     diagonal second-order central moments relaxes with omega_bulk, the
  *     deviator and the off-diagonal ones with omega.  omega_bulk = omega
  *     is the paper's setting.
- *   - Walls: halfway bounce-back (the curved treatment of Sec. 2.2 at
- *     wall distance one half).  Inlet: bounce-back from a wall moving
- *     with the prescribed inlet velocity of Eq. (12) at the inlet cell,
- *     wall density 1.  Outlet: zero gradient, sources beyond the last
- *     x plane are taken from the last x plane.
+ *   - Walls: halfway bounce-back by default (the curved treatment of
+ *     Sec. 2.2 at wall distance one half); the linear interpolated rule
+ *     with per-link fractions after oracle_set_wall_distances (see there).
+ *     Inlet: bounce-back from a wall moving with the prescribed inlet
+ *     velocity of Eq. (12) at the inlet cell, wall density 1.  Outlet:
+ *     zero gradient by default, sources beyond the last x plane are taken
+ *     from the last x plane; constant pressure by non-equilibrium
+ *     extrapolation after oracle_set_outlet (see there).
  */
 #include <math.h>
 #include <stdint.h>

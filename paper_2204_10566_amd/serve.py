@@ -6,10 +6,9 @@ creation and upload) runs on a worker pool; the serving thread admits
 prepared domains first-come-first-served while the batch's HBM budget has
 room, advances every resident domain with packed, graph-replayed launches
 (one per parity class and time step), and hands finished domains back to the
-pool, which copies
-their density and velocity to the host.  A domain's state stays on the
-device from admission to completion.  The same trace can be served one solve
-at a time for comparison.
+pool, which copies their density and velocity to the host.  A domain's state
+stays on the device from admission to completion.  The same trace can be
+served one solve at a time for comparison.
 
 Latency of a request = time from its arrival to its result on the host.
 """
@@ -21,6 +20,7 @@ import concurrent.futures as cf
 import json
 import math
 import sys
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -47,7 +47,7 @@ class Outcome:
         return self.done - self.arrival
 
 
-_timing_lock = __import__("threading").Lock()
+_timing_lock = threading.Lock()
 _timing = collections.Counter()
 
 
