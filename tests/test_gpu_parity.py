@@ -191,6 +191,45 @@ def test_full_size_nozzle_sampled(capi, orc, which, storage):
     d.destroy()
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_tgv320_probe_sampled(capi, orc, storage):
+    """The benchmark's bandwidth probe: the periodic Taylor-Green vortex on
+    320^3 cells (3.5 GB of FP32 populations, the largest array of the tests,
+    with byte offsets up to 3.5e9 of the 4 GiB the buffer instructions
+    address), 3 steps in the benchmark's launch configuration.  Sampled
+    cells (the last tiles of the array, the periodic faces, random) against
+    the oracle's dependency-cone run, and the total mass of all cells
+    against its initial value (conserved by the update up to rounding)."""
+    n, tau = 320, 0.6
+    fl = I.periodic_box(n)
+    u0 = I.taylor_green_velocity(n, n, n, 0.05).astype(np.float32)
+    say(f"tgv {n}^3 {storage} 3 steps")
+    d = run_gpu(capi, fl, 7, 0, tau=tau, u0=u0, storage=storage)
+    rho, _ = d.moments()
+    m0 = float(rho.astype(np.float64).sum())
+    d.step(3)
+    rho, _ = d.moments()
+    m1 = float(rho.astype(np.float64).sum())
+    fg = d.populations().reshape(27, -1)
+    d.destroy()
+    ncells = fl.size
+    rng = np.random.default_rng(3)
+    cells = np.unique(np.concatenate([
+        np.arange(ncells - 130, ncells),  # the last two tiles and a bit
+        np.arange(0, 70),  # the first tile, periodic neighbour of the last
+        rng.integers(0, n, 40) * n * n + rng.integers(0, n, 40) * n,  # x = 0
+        rng.integers(0, n, 40) * n * n + rng.integers(0, n, 40) * n + (n - 1),  # x = n - 1
+        rng.choice(ncells, 100, replace=False),
+    ]))
+    st, fo = orc.run_cells(fl, cells, orc.rates_vector(1 / tau), 3, periodic=7, u0=u0)
+    assert st == 0
+    err = float(np.abs(fg[:, cells] - fo).max())
+    drift = abs(m1 - m0) / m0
+    say(f"tgv {n}^3 {storage}: {cells.size} cells, max abs err {err:.3e}, mass drift {drift:.2e}")
+    assert err <= (1e-6 if storage == "fp32" else 2e-5)
+    assert drift <= 1e-6
+
+
 def test_fp16_shifted_tgv32(capi, orc):
     n, tau = 32, 0.6
     fl = I.periodic_box(n)
