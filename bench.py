@@ -273,7 +273,7 @@ def stability_leg(capi, stream):
     return out
 
 
-def cpu_baseline(cfg, nsteps=3):
+def cpu_baseline(cfg, nsteps=4):
     import numpy as np
 
     import oracle
