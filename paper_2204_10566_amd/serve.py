@@ -141,6 +141,7 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
     waiting = collections.deque()    # (req, domain) prepared, not yet admitted
     resident = {}                    # slot -> (req, domain, updated cells)
     resident_cells = 0
+    peak_cells = 0                   # most updated cells resident at once
     idle_ticks = 0                   # loop turns with nothing resident
     finishing = []                   # (req, future)
     t0 = time.perf_counter()
@@ -168,6 +169,7 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
                 waiting.popleft()
                 resident[slot] = (r, d, nupd)
                 resident_cells += nupd
+                peak_cells = max(peak_cells, resident_cells)
                 outs[r.rid].admitted = now()
             _, enq, done, _ = batch.stats()
             if resident and enq - done < max_ahead * steps_per_tick:
@@ -198,6 +200,7 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
     res = [outs[r.rid] for r in reqs]
     s = summarise("continuous-batching", res, wall, budget_bytes)
     s["work_cap_cells"] = work_cap_cells
+    s["peak_resident_cells"] = peak_cells
     s["order"] = order
     s["idle_loop_turns"] = idle_ticks
     return res, s

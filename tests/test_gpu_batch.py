@@ -162,6 +162,34 @@ def test_serving_alone_equals_mix(capi):
         assert np.array_equal(o.rho, a.rho) and np.array_equal(o.u, a.u), f"request {o.rid} differs"
 
 
+def test_serving_work_cap(capi):
+    """With a cap on resident updated cells, admission holds requests back
+    until earlier ones finish (never more than the cap resident, unless a
+    single request exceeds it), and every result still equals the request
+    served alone."""
+    from paper_2204_10566_amd import serve
+
+    tr = I.serving_trace(count=6, rate=200.0, seed=7, steps_lo=20, steps_hi=60)
+    for r in tr:
+        n = 32 if r.rid % 2 else 40
+        r.nozzle = I.Nozzle(n=n, length=4 * n, R=n / 4.0, r_throat=n / 4.0 * 0.4, inlet_len=n / 2.0,
+                            throat_len=n)
+    say("serving with a cap of two small requests")
+    alone, _ = serve.serve_serial(tr, storage="fp16s", keep_fields=True, realtime=False)
+    cells = {o.rid: o.updated_cells for o in alone}
+    cap = sorted(cells.values())[-1] + sorted(cells.values())[0]
+    mix, s_mix = serve.serve_continuous(tr, storage="fp16s", budget_bytes=1 << 32, steps_per_tick=4,
+                                        keep_fields=True, realtime=False, work_cap_cells=cap)
+    say(f"  cap {cap}, peak resident {s_mix['peak_resident_cells']}")
+    assert 0 < s_mix["peak_resident_cells"] <= max(cap, max(cells.values()))
+    assert s_mix["peak_resident_cells"] < sum(cells.values())
+    by = {o.rid: o for o in alone}
+    for o in mix:
+        a = by[o.rid]
+        assert o.status == a.status
+        assert np.array_equal(o.rho, a.rho) and np.array_equal(o.u, a.u), f"request {o.rid} differs"
+
+
 def test_unstable_domain_is_evicted(capi):
     """A domain that goes unstable inside a batch is reported long before
     its step count, released as unstable, and the other domains finish with
