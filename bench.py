@@ -286,16 +286,44 @@ def cpu_baseline(cfg, nsteps=4):
                         uin=cfg["uin"])
     t2 = time.perf_counter()
     n_upd = int(((fl == 0) | (fl == 3)).sum())
+    threads = oracle.max_threads()
+    # one thread, on a small sample: the periodic TGV 32^3, 3 steps
+    from paper_2204_10566_amd import inputs as I
+
+    n1, s1 = 32, 3
+    fl1 = I.periodic_box(n1)
+    f1 = oracle.init_fields(fl1, None, I.taylor_green_velocity(n1, n1, n1, 0.05))
+    oracle.set_threads(1)
+    try:
+        t3 = time.perf_counter()
+        st1, _ = oracle.step(fl1, f1, oracle.rates_vector(1.0 / 0.6), s1, periodic=7)
+        t4 = time.perf_counter()
+    finally:
+        oracle.set_threads(threads)
     return {
         "value": round(n_upd * nsteps / (t2 - t1) / 1e6, 4),
         "unit": "MLUPS",
-        "cores": oracle.max_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": f"{nsteps} FP64 oracle steps (dense 27x27 transform + Gaussian elimination per cell) of the "
                   f"full 96x96x768 nozzle ({n_upd} updated cells) from the plug-flow start; "
                   f"{t2 - t1:.1f} s stepping, {t1 - t0:.1f} s equilibrium init not counted",
         "status": int(st),
+        "single_thread": {"value": round(n1 ** 3 * s1 / (t4 - t3) / 1e6, 4), "unit": "MLUPS", "cores": 1,
+                          "sample": f"{s1} FP64 oracle steps of the periodic TGV {n1}^3, {t4 - t3:.1f} s",
+                          "status": int(st1)},
+        "host": {"cpu": _cpu_model(), "logical_cpus": os.cpu_count()},
     }
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():

@@ -76,6 +76,7 @@ def lib():
                                        dp, ctypes.c_int, ctypes.c_long, lp, dp]
         L.oracle_run_cells.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -266,3 +267,8 @@ def run_cells(flags, cells, rates, nsteps, periodic=0, uin=None, rho0=None, u0=N
 
 def max_threads():
     return lib().oracle_max_threads()
+
+
+def set_threads(n: int):
+    """Threads of the following oracle calls (n <= 0: one per processor)."""
+    lib().oracle_set_threads(int(n))

@@ -776,3 +776,13 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the following calls (n <= 0: one per processor). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
