@@ -238,3 +238,37 @@ def test_collision_relaxes_each_central_moment(orc):
             else:
                 ref = (1 - high[n - 3]) * m[k]
             assert abs(ms[k] - ref) < 1e-14, (k, ms[k], ref)
+
+
+def test_cell_moments_brute_force(orc):
+    """Density and velocity of a population set (Sec. 2.1): the plain sums
+    over the lattice, built here from the documented velocity order."""
+    rng = np.random.default_rng(8)
+    c = lattice()
+    for _ in range(5):
+        f = random_state(orc, rng, 0.05)
+        rho, u = orc.cell_moments(f)
+        assert abs(rho - f.sum()) < 1e-15
+        assert np.abs(u - (c.T @ f) / f.sum()).max() < 1e-15
+
+
+def test_collide_field_is_per_cell_collision(orc):
+    """The field collision applies the one-cell collision to every updated
+    cell (fluid, outlet) and leaves solid and inlet cells as they are."""
+    rng = np.random.default_rng(9)
+    fl = np.zeros((2, 3, 4), np.uint8)
+    fl[0, 1, 2] = 1  # solid
+    fl[1, 0, 0] = 2  # inlet
+    fl[1, 2, 3] = 3  # outlet
+    f = np.stack([random_state(orc, rng, 0.05) for _ in range(fl.size)], axis=1).reshape((27,) + fl.shape)
+    rates = orc.rates_vector(1 / 0.6, 0.9, order_rates=[1.1, 1.2, 0.8, 1.3])
+    st, fo = orc.collide_field(fl, f, rates)
+    assert st == 0
+    f2, fo2 = f.reshape(27, -1), fo.reshape(27, -1)
+    for cell, flag in enumerate(fl.ravel()):
+        if flag in (0, 3):
+            st1, ref = orc.collide(f2[:, cell], rates)
+            assert st1 == 0
+            assert np.array_equal(fo2[:, cell], ref)
+        else:
+            assert np.array_equal(fo2[:, cell], f2[:, cell])
