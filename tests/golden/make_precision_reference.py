@@ -6,8 +6,15 @@ with the paper's rates (omega_bulk = 1/tau, omega_high = 1), over the
 instability amplifies round-off).  Stores rho - 1 and u at the updated
 cells, in ascending cell order, one file per window.
 
+With --perturb EPS it writes the same windows from an initial velocity
+multiplied by (1 + EPS xi), xi standard normal per cell and component
+(numpy PCG64, seed 1), in one run (the 200-step state on the way to 2000):
+the divergence of two FP64 runs that differ by about FP32 rounding, which
+shows how much the flow itself amplifies a perturbation of that size.
+
 Run from the repository root:
     python tests/golden/make_precision_reference.py [steps ...]   (default: 200 2000)
+    python tests/golden/make_precision_reference.py --perturb 1e-7
 Only the oracle and the seeded input generators are used.
 """
 import os
@@ -25,8 +32,18 @@ from paper_2204_10566_amd import inputs as I  # noqa: E402
 WINDOWS = (200, 2000)
 
 
-def out_path(steps):
-    return os.path.join(os.path.dirname(os.path.abspath(__file__)), f"precision_re6500_quarter_{steps}.npz")
+def out_path(steps, perturbed=False):
+    tag = "_perturbed" if perturbed else ""
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), f"precision_re6500_quarter_{steps}{tag}.npz")
+
+
+def save(out, fl, f, steps, tau, t0, **extra):
+    rho, u = oracle.moments(fl, f)
+    upd = ((fl == I.FLUID) | (fl == I.OUTLET)).ravel()
+    np.savez_compressed(out, steps=steps, tau=tau, drho=(rho.ravel()[upd] - 1.0).astype(np.float32),
+                        u=u.reshape(3, -1)[:, upd].astype(np.float32), threads=oracle.max_threads(),
+                        seconds=time.time() - t0, **extra)
+    print(f"wrote {out} in {time.time() - t0:.0f} s", flush=True)
 
 
 def write(steps):
@@ -40,16 +57,33 @@ def write(steps):
     st, f = oracle.step(fl, f, oracle.rates_vector(1.0 / cfg["tau"]), steps, periodic=0, uin=uin)
     if st != 0:
         raise SystemExit(f"oracle status {st}")
-    rho, u = oracle.moments(fl, f)
-    upd = ((fl == I.FLUID) | (fl == I.OUTLET)).ravel()
-    np.savez_compressed(out, steps=steps, tau=cfg["tau"], drho=(rho.ravel()[upd] - 1.0).astype(np.float32),
-                        u=u.reshape(3, -1)[:, upd].astype(np.float32), threads=oracle.max_threads(),
-                        seconds=time.time() - t0)
-    print(f"wrote {out} in {time.time() - t0:.0f} s")
+    save(out, fl, f, steps, cfg["tau"], t0)
+
+
+def write_perturbed(eps):
+    cfg = I.nozzle_config("re6500_quarter")
+    fl = cfg["flags"]
+    uin = cfg["uin"].astype(np.float32)
+    u0 = cfg["u0"].astype(np.float32).astype(np.float64)
+    u0 = u0 * (1.0 + eps * np.random.default_rng(1).standard_normal(u0.shape))
+    rates = oracle.rates_vector(1.0 / cfg["tau"])
+    t0 = time.time()
+    f = oracle.init_fields(fl, None, u0)
+    done = 0
+    for steps in WINDOWS:
+        st, f = oracle.step(fl, f, rates, steps - done, periodic=0, uin=uin)
+        if st != 0:
+            raise SystemExit(f"oracle status {st}")
+        done = steps
+        save(out_path(steps, True), fl, f, steps, cfg["tau"], t0, perturbation=eps)
 
 
 def main():
-    for steps in ([int(a) for a in sys.argv[1:]] or WINDOWS):
+    args = sys.argv[1:]
+    if args[:1] == ["--perturb"]:
+        write_perturbed(float(args[1]))
+        return
+    for steps in ([int(a) for a in args] or WINDOWS):
         write(steps)
 
 

@@ -76,7 +76,7 @@ def test_curved_walls_random_states(capi, orc, storage, shape, rates):
     q = random_q(fl, 7)
     f0 = random_pops(fl, 5)
     upd = updated(fl)
-    tol = 4e-7 if storage == "fp32" else 2e-3
+    tol = 4e-7 if storage == "fp32" else 5e-5  # per step; FP16S: 2^-11 |f - w| per store
     for steps in (1, 6):
         say(f"curved walls {shape} {storage} rates={rates} steps={steps}")
         d = capi.Domain(fl, periodic=4, storage=storage)
@@ -106,7 +106,7 @@ def test_curved_walls_state_access_and_change(capi, orc, storage):
     rates = (1 / 0.6, 1.1, 1.0)
     rv = orc.rates_vector(*rates)
     upd = updated(fl)
-    tol = 4e-7 if storage == "fp32" else 2e-3
+    tol = 4e-7 if storage == "fp32" else 5e-5  # per step; FP16S: 2^-11 |f - w| per store
     say(f"curved walls state access {storage}")
     d = capi.Domain(fl, periodic=4, storage=storage)
     d.set_rates(*rates)

@@ -64,7 +64,7 @@ def test_pressure_outlet_random_states(capi, orc, storage, shape):
     f0 = random_pops(fl, 5)
     rates = (1 / 0.57, 1.2, 1.0)
     upd = updated(fl)
-    tol = 4e-7 if storage == "fp32" else 2e-3
+    tol = 4e-7 if storage == "fp32" else 5e-5  # per step; FP16S: 2^-11 |f - w| per store
     for steps in (1, 6):
         say(f"pressure outlet {shape} {storage} steps={steps}")
         d = capi.Domain(fl, periodic=4, storage=storage)
@@ -93,7 +93,7 @@ def test_pressure_outlet_state_access_and_change(capi, orc, storage):
     rates = (1 / 0.6, 1.1, 1.0)
     rv = orc.rates_vector(*rates)
     upd = updated(fl)
-    tol = 4e-7 if storage == "fp32" else 2e-3
+    tol = 4e-7 if storage == "fp32" else 5e-5  # per step; FP16S: 2^-11 |f - w| per store
     say(f"pressure outlet state access {storage}")
     d = capi.Domain(fl, periodic=4, storage=storage)
     d.set_rates(*rates)

@@ -7,7 +7,10 @@ Tolerances (FP32 storage and arithmetic against FP64):
     ten FP32 ulps of the largest population (8/27), which bounds the rounding
     of the ~600 FP32 operations of one update;
   - nozzle geometries: velocity error relative to the peak velocity;
-  - FP16 shifted storage: velocity relative L2 <= 1e-3.
+  - FP16 shifted storage: velocity relative L2 <= 1e-3; from random
+    populations, max abs <= 5e-5 per step (each store rounds 2^14 (f - w)
+    to 11 significant bits, at most 2^-11 |f - w|, and these states keep
+    |f - w| near 0.01).
 """
 import math
 import sys
@@ -323,7 +326,7 @@ def test_state_access_between_odd_and_even_steps(capi, orc, storage):
     rates = (1 / 0.57, 1.1, 1.2)
     rv = orc.rates_vector(*rates)
     upd = updated(fl)
-    tol = 4e-7 if storage == "fp32" else 2e-3
+    tol = 4e-7 if storage == "fp32" else 5e-5  # per step; FP16S: 2^-11 |f - w| per store
     say(f"odd/even state access {storage}")
     d = capi.Domain(fl, periodic=4, storage=storage)
     d.set_rates(*rates)
@@ -374,7 +377,7 @@ def test_row_aligned_domain(capi, orc, storage):
     f0 = random_pops(orc, fl, 17)
     rates = (1 / 0.56, 1.3, 1.0)
     upd = updated(fl)
-    tol = 4e-7 if storage == "fp32" else 2e-3
+    tol = 4e-7 if storage == "fp32" else 5e-5  # per step; FP16S: 2^-11 |f - w| per store
     for steps in (1, 6):
         say(f"row-aligned channel {storage} steps={steps}")
         d = capi.Domain(fl, periodic=4, storage=storage)
@@ -406,7 +409,7 @@ def test_row_aligned_periodic_x(capi, orc, storage, periodic):
     f0 = random_pops(orc, fl, 61)
     rates = (1 / 0.59, 1.2, 1.0)
     upd = updated(fl)
-    tol = 4e-7 if storage == "fp32" else 2e-3
+    tol = 4e-7 if storage == "fp32" else 5e-5  # per step; FP16S: 2^-11 |f - w| per store
     for steps in (1, 4):
         say(f"row-aligned periodic x {storage} periodic={periodic} steps={steps}")
         d = capi.Domain(fl, periodic=periodic, storage=storage)
