@@ -12,7 +12,9 @@ cases); FP16S 5e-5.  Each FP16S store rounds 2^14 (f - w) to 11
 significant bits, an error of at most 2^-11 |f - w|; these states start
 with |f - w| <= 0.013 (6e-6 per store) and the collision and the boundary
 terms move them somewhat further from w (measured: at most 7.3e-6 after one
-step, 9.5e-6 after several)."""
+step, 9.5e-6 after several).  A further set of cases stores BF16S: 8
+significant bits, at most 2^-8 |f - w| (5e-5) per store; bound 2e-4 per
+step."""
 import sys
 
 import numpy as np
@@ -37,7 +39,8 @@ def capi():
     return capi
 
 
-def make_case(k):
+def make_case(k, storage_override=None):
+    """Configuration k; storage_override, if given, replaces the drawn storage."""
     rng = np.random.default_rng(1000 + k)
     nx = int(rng.choice([17, 23, 64, 70, 128]))
     ny, nz = int(rng.integers(4, 11)), int(rng.integers(3, 8))
@@ -77,12 +80,23 @@ def make_case(k):
     uin[:, fl == I.INLET] = 0.03 * rng.uniform(-1, 1, (3, n_in))
     f0 = I.random_populations(fl.shape, 2000 + k).astype(np.float32).astype(np.float64)
     return dict(fl=fl, periodic=periodic, outlet=outlet, q=q, omega=omega, omega_b=omega_b, order=order,
-                storage=storage, steps=steps, uin=uin if n_in else None, f0=f0)
+                storage=storage_override or storage, steps=steps, uin=uin if n_in else None, f0=f0)
+
+
+TOL_PER_STEP = {"fp32": 4e-7, "fp16s": 5e-5, "bf16s": 2e-4}
 
 
 @pytest.mark.parametrize("k", range(N_CASES))
 def test_random_configuration(capi, orc, k):
-    c = make_case(k)
+    check_case(capi, orc, k, make_case(k))
+
+
+@pytest.mark.parametrize("k", range(16))
+def test_random_configuration_bf16(capi, orc, k):
+    check_case(capi, orc, k, make_case(k, "bf16s"))
+
+
+def check_case(capi, orc, k, c):
     fl = c["fl"]
     say(f"case {k}: shape {fl.shape} periodic {c['periodic']} {c['storage']} steps {c['steps']} "
         f"outlet {c['outlet']} curved {c['q'] is not None} inlet cells {int((fl == I.INLET).sum())} "
@@ -107,6 +121,6 @@ def test_random_configuration(capi, orc, k):
     assert st == 0
     upd = (fl == I.FLUID) | (fl == I.OUTLET)
     err = float(np.abs(fg[:, upd] - fo[:, upd]).max()) if upd.any() else 0.0
-    tol = (4e-7 if c["storage"] == "fp32" else 5e-5) * c["steps"]
+    tol = TOL_PER_STEP[c["storage"]] * c["steps"]
     say(f"  max abs err {err:.3e} (bound {tol:.1e})")
     assert err <= tol
