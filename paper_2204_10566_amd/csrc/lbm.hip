@@ -358,6 +358,7 @@ KDomain kdomain(const lbm_domain *d)
     for (int n = 0; n < 4; ++n)
         k.omega_o[n] = (float)d->omega_o[n];
     k.outlet = d->outlet_kind == LBM_OUTLET_PRESSURE ? 1u : 0u;
+    k.high1 = d->high1() ? 1u : 0u;
     k.rho_out = (float)d->rho_out;
     return k;
 }

@@ -105,6 +105,7 @@ struct KDomain {
     // [step0, step0 + nsteps), starting in phase ph0.
     uint32_t step0, nsteps, ph0, pad;
     uint32_t outlet;         // 0: zero-gradient outlet, 1: constant pressure rho_out / 3 (kernel variant kVarPressure)
+    uint32_t high1;          // every rate of order >= 3 is one (see collide_lane)
     float rho_out;
     const float2 *bzc;       // curved-wall coefficients, [27][64] per wall tile (see curved_walls)
     float *bzaux;            // f*_k of the lanes' previous step, [27][64] per wall tile
@@ -445,6 +446,26 @@ __device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega
     return rho;
 }
 
+// Collision of a lane in kernel variant V.  In a packed launch a step runs
+// one variant for every domain, the general collision as soon as one domain
+// needs it (DYN); a domain whose higher-order rates are all one then still
+// takes the reduced form, chosen per domain (the branch is wave-uniform), so
+// that it ends bit for bit where it ends alone.
+template <int V, bool DYN>
+__device__ __forceinline__ float collide_lane(const KDomain &d, float (&f)[Q], float &ux, float &uy, float &uz,
+                                              float (&m2)[6])
+{
+    if constexpr ((V & kVarH1) != 0) {
+        return collide<true>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+    } else if constexpr (DYN) {
+        if (d.high1)
+            return collide<true>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+        return collide<false>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+    } else {
+        return collide<false>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The step, in place on one population array (Sec. 2.1, Eq. (6); boundary
 // rules of Sec. 2.2).  Steps alternate between two phases, so that each
@@ -631,7 +652,7 @@ __device__ __forceinline__ uint32_t slot_of(const KDomain &d, const Coords &C, i
 
 // Phase 0 -> 1.  EDGE: the tile has cells on the outlet plane (tile entry
 // `edge`); the other tiles compile without the outlet handling.
-template <int ST, int V, bool EDGE>
+template <int ST, int V, bool EDGE, bool DYN = false>
 __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     using S = Storage<ST>;
@@ -675,7 +696,7 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
     }
 
     float ux, uy, uz, m2[6];
-    const float rho = collide<(V & kVarH1) != 0>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+    const float rho = collide_lane<V, DYN>(d, f, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
     if constexpr ((V & kVarCurved) != 0) {
         if (wall && rec.bz)
@@ -787,7 +808,7 @@ __device__ __forceinline__ RowAddr row_addr(const KDomain &d, const TileRec &rec
 
 // Phase 0 -> 1 for a tile of a row-aligned domain: stream_tile_t with the
 // addressing above.  EDGE: the tile holds a cell of the outlet plane.
-template <int ST, int V, bool EDGE>
+template <int ST, int V, bool EDGE, bool DYN = false>
 __device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     using S = Storage<ST>;
@@ -830,7 +851,7 @@ __device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec
     }
 
     float ux, uy, uz, m2[6];
-    const float rho = collide<(V & kVarH1) != 0>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+    const float rho = collide_lane<V, DYN>(d, f, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
     if constexpr ((V & kVarCurved) != 0) {
         if (wall && rec.bz)
@@ -881,19 +902,19 @@ __device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec
     }
 }
 
-template <int ST, int V>
+template <int ST, int V, bool DYN = false>
 __device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     if (d.rowtiles) {
         if (rec.edge)
-            stream_tile_rows<ST, V, true>(d, rec, lane);
+            stream_tile_rows<ST, V, true, DYN>(d, rec, lane);
         else
-            stream_tile_rows<ST, V, false>(d, rec, lane);
+            stream_tile_rows<ST, V, false, DYN>(d, rec, lane);
     } else {
         if (rec.edge)
-            stream_tile_t<ST, V, true>(d, rec, lane);
+            stream_tile_t<ST, V, true, DYN>(d, rec, lane);
         else
-            stream_tile_t<ST, V, false>(d, rec, lane);
+            stream_tile_t<ST, V, false, DYN>(d, rec, lane);
     }
 }
 
@@ -924,7 +945,7 @@ __device__ __forceinline__ void local_load(const KDomain &d, const TileRec &rec,
 // the central second-order Hermite moments M_ab (Sec. 2.2, Eqs. (15)-(19);
 // App. A, Eqs. (A.7)-(A.8)); sums of component c at stats[c * sstride +
 // 64 ord + lane].
-template <int ST, int V>
+template <int ST, int V, bool DYN = false>
 __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &rec, uint32_t lane, float (&f)[Q])
 {
     using S = Storage<ST>;
@@ -939,7 +960,7 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
             curved_walls(d, rec, lane, f);
     }
     float ux, uy, uz, m2[6];
-    const float rho = collide<(V & kVarH1) != 0>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+    const float rho = collide_lane<V, DYN>(d, f, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
     if constexpr ((V & kVarCurved) != 0) {
         if (rec.wall >= 0 && rec.bz)
@@ -974,12 +995,12 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
     }
 }
 
-template <int ST, int V>
+template <int ST, int V, bool DYN = false>
 __device__ __forceinline__ void local_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     float f[Q];
     local_load<ST>(d, rec, lane, f);
-    local_finish<ST, V>(d, rec, lane, f);
+    local_finish<ST, V, DYN>(d, rec, lane, f);
 }
 
 // Inlet terms of the inlet tiles: for inlet link i of a cell, the moving-
@@ -1093,9 +1114,9 @@ __global__ __launch_bounds__(kBlock) void k_collide_batched(const KDomain *__res
         if (k >= dd.nsteps || ((dd.ph0 + k) & 1u) != PHASE)
             continue;
         if (PHASE == 0u)
-            stream_tile<ST, V>(dd, rec, lane);
+            stream_tile<ST, V, (V & kVarH1) == 0>(dd, rec, lane);
         else
-            local_tile<ST, V>(dd, rec, lane);
+            local_tile<ST, V, (V & kVarH1) == 0>(dd, rec, lane);
     }
 }
 

@@ -101,16 +101,7 @@ def check_case(capi, orc, k, c):
     say(f"case {k}: shape {fl.shape} periodic {c['periodic']} {c['storage']} steps {c['steps']} "
         f"outlet {c['outlet']} curved {c['q'] is not None} inlet cells {int((fl == I.INLET).sum())} "
         f"omega {c['omega']:.4f} omega_b {c['omega_b']:.3f} orders {np.round(c['order'], 3).tolist()}")
-    d = capi.Domain(fl, periodic=c["periodic"], storage=c["storage"])
-    d.set_rates(c["omega"], c["omega_b"], 1.0)
-    d.set_order_rates(*c["order"])
-    if c["outlet"]:
-        d.set_outlet(*c["outlet"])
-    if c["q"] is not None:
-        d.set_wall_distances(c["q"])
-    if c["uin"] is not None:
-        d.set_inlet(c["uin"])
-    d.set_populations(c["f0"])
+    d = build_domain(capi, c, c["storage"])
     fs = d.populations().astype(np.float64)
     d.step(c["steps"])
     fg = d.populations()
@@ -124,3 +115,45 @@ def check_case(capi, orc, k, c):
     tol = TOL_PER_STEP[c["storage"]] * c["steps"]
     say(f"  max abs err {err:.3e} (bound {tol:.1e})")
     assert err <= tol
+
+
+def build_domain(capi, c, storage):
+    d = capi.Domain(c["fl"], periodic=c["periodic"], storage=storage)
+    d.set_rates(c["omega"], c["omega_b"], 1.0)
+    d.set_order_rates(*c["order"])
+    if c["outlet"]:
+        d.set_outlet(*c["outlet"])
+    if c["q"] is not None:
+        d.set_wall_distances(c["q"])
+    if c["uin"] is not None:
+        d.set_inlet(c["uin"])
+    d.set_populations(c["f0"])
+    return d
+
+
+def test_random_mix_packed_equals_alone(capi):
+    """Eight random configurations packed into one batch (FP16S; reduced and
+    general higher-order rates, curved walls, both outlets, ragged and
+    row-aligned grids mixed) with different step counts: each ends bit for
+    bit where it ends alone."""
+    cases = [make_case(k, "fp16s") for k in range(8)]
+    steps = [3 * c["steps"] + k for k, c in enumerate(cases)]
+    h1 = [all(v == 1.0 for v in c["order"]) for c in cases]
+    assert any(h1) and not all(h1)
+    say(f"packed random mix: steps {steps}, reduced collision {h1}")
+    alone = []
+    for c, n in zip(cases, steps):
+        d = build_domain(capi, c, "fp16s")
+        d.step(n)
+        alone.append(d.populations())
+        d.destroy()
+    doms = [build_domain(capi, c, "fp16s") for c in cases]
+    b = capi.Batch(1 << 32, "fp16s")
+    slots = [b.admit(d, n) for d, n in zip(doms, steps)]
+    b.step(max(steps))
+    assert sorted(b.poll(wait=True)) == sorted(slots)
+    for k, s in enumerate(slots):
+        b.release(s)
+        assert np.array_equal(doms[k].populations(), alone[k]), f"case {k} differs"
+        doms[k].destroy()
+    b.destroy()
