@@ -168,19 +168,31 @@ def precision_leg(capi, torch, stream):
         res = {"workload": "128x128x1536 Re 6500 nozzle at quarter scale (32x32x384), inlet noise 1 %, "
                            f"{int(ref['steps'])} steps from plug flow, tau={float(ref['tau']):.7f}",
                "reference": f"tests/golden/precision_re6500_quarter_{steps}.npz (FP64 oracle)"}
-        for st in ("fp32", "fp16s", "bf16s"):
+        def run(st, u0):
             d = capi.Domain(fl, periodic=0, storage=st, stream=stream.cuda_stream)
             d.set_params(cfg["tau"])
             d.set_inlet(cfg["uin"].astype(np.float32))
-            d.init_fields(None, cfg["u0"].astype(np.float32))
+            d.init_fields(None, u0)
             rc = d.step_status(int(ref["steps"]))
             rho, u = d.moments()
             d.destroy()
-            ug = u.reshape(3, -1)[:, upd].astype(np.float64)
-            dr = rho.ravel()[upd].astype(np.float64) - 1.0
+            return rc, rho.ravel()[upd].astype(np.float64) - 1.0, u.reshape(3, -1)[:, upd].astype(np.float64)
+
+        u32 = {}
+        for st in ("fp32", "fp16s", "bf16s"):
+            rc, dr, ug = run(st, cfg["u0"].astype(np.float32))
+            u32[st] = ug
             res[st] = {"e_u": float(np.linalg.norm(ug - ur) / np.linalg.norm(ur)),
                        "e_p": float(np.linalg.norm(dr - rr) / np.linalg.norm(rr - rr.mean())), "status": int(rc)}
             log(f"precision {steps} steps {st}: {res[st]}")
+        # sensitivity of the flow itself: FP32 from an initial velocity
+        # perturbed by 1e-7 relative (about FP32 rounding) against FP32
+        u0 = cfg["u0"].astype(np.float32).astype(np.float64)
+        u0p = (u0 * (1.0 + 1e-7 * np.random.default_rng(1).standard_normal(u0.shape))).astype(np.float32)
+        rc, _, up = run("fp32", u0p)
+        res["fp32_perturbed_1e-7_vs_fp32"] = {"e_u": float(np.linalg.norm(up - u32["fp32"]) /
+                                                          np.linalg.norm(u32["fp32"])), "status": int(rc)}
+        log(f"precision {steps} steps fp32 perturbed 1e-7 vs fp32: {res['fp32_perturbed_1e-7_vs_fp32']}")
         out[f"quarter_scale_vs_fp64_{steps}_steps"] = res
     cfg = I.nozzle_config("re6500")
     for k in ("uin", "u0"):
