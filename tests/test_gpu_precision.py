@@ -11,13 +11,14 @@ Errors: e_u = |u - u_ref|_2 / |u_ref|_2 and e_p = |rho - rho_ref|_2 /
 FP32 storage rounds each stored population to 2^-24 relative, FP16-shifted
 storage to 2^-11 of (f - w) 2^14, i.e. about 3e-5 absolute on f, BF16 to
 2^-8 of (f - w).  Over the first 200 steps the difference is that rounding,
-already amplified by the nearly inviscid flow (measured: FP32 5.5e-5, FP16
-5.3e-4, BF16 4.9e-3): FP32 is held to 1e-4, FP16 to the 1e-3 velocity error
-the method is held to, BF16 to 1e-2.  Over 2000 steps the jet behind the
-throat is unstable at this Reynolds number and amplifies any rounding (FP32
-included) by orders of magnitude (measured: FP32 2.8e-3, FP16 3.4e-2, BF16
-0.48, where BF16 has lost the flow's detail), so that window reports the
-divergence and bounds it loosely."""
+accumulated step by step (measured: FP32 5.5e-5, FP16 5.3e-4, BF16 4.9e-3):
+FP32 is held to 1e-4, FP16 to the 1e-3 velocity error the method is held
+to, BF16 to 1e-2.  Between steps 200 and 2000 the jet behind the throat is
+unstable at this Reynolds number: two FP64 oracle runs from starts 1e-7
+apart drift 200-fold further apart (a CPU test pins this on the stored
+fields), and the rounding of every step is amplified alike (measured: FP32
+2.8e-3, FP16 3.4e-2, BF16 0.48, where BF16 has lost the flow's detail), so
+that window reports the divergence and bounds it loosely."""
 import os
 
 import numpy as np
