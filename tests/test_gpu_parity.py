@@ -12,7 +12,6 @@ Tolerances (FP32 storage and arithmetic against FP64):
     to 11 significant bits, at most 2^-11 |f - w|, and these states keep
     |f - w| near 0.01).
 """
-import math
 import sys
 
 import numpy as np
