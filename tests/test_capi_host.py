@@ -92,3 +92,28 @@ def test_null_handles(capi):
     assert capi.lbm_destroy(None) == capi.ERR_ARG
     assert capi.lbm_batch_step(None, 1) == capi.ERR_ARG
     assert capi.lbm_batch_destroy(None) == capi.ERR_ARG
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library the binding refuses to import (there is no
+    CPU fallback for any step of the update)."""
+    import subprocess
+    import sys
+
+    env = dict(os.environ, LBM_LIBRARY=str(tmp_path / "missing" / "liblbm.so"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2204_10566_amd.capi"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "no CPU fallback" in r.stderr
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; asked for more it exits with status 2 and
+    says why, before touching a device."""
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
