@@ -247,3 +247,54 @@ def test_graph_replays_match_eager_steps(capi):
     for _ in range(207):
         e.step(1)
     assert np.array_equal(g.populations(), e.populations())
+
+
+def test_batch_state_errors(capi):
+    """A domain resident in a batch refuses stand-alone calls
+    (LBM_ERR_STATE); the batch refuses a second admission of it, a domain of
+    another storage, a non-positive step count, releasing a slot before its
+    steps have completed or a slot that does not exist, and destruction while
+    it holds domains.  After release the domain works stand-alone again."""
+    import ctypes
+
+    spec = small_specs(1, 21)[0]
+    d = build(capi, spec, "fp16s")
+    other = build(capi, spec, "fp32")
+    b = capi.Batch(1 << 32, "fp16s")
+    slot = b.admit(d, 10)
+    say("batch state errors")
+    h = d.h
+    pops = np.zeros(27 * d.ncells, np.float32).ctypes.data_as(capi._fp)
+    n_in = int(d.info().n_inlet)
+    uin = np.zeros(max(1, 3 * n_in), np.float32).ctypes.data_as(capi._fp)
+    state = {
+        "lbm_step": capi.lbm_step(h, 1),
+        "lbm_set_params": capi.lbm_set_params(h, 0.6, 1 / 0.6, 1.0),
+        "lbm_set_rates": capi.lbm_set_rates(h, 1.5, 1.5, 1.0),
+        "lbm_set_order_rates": capi.lbm_set_order_rates(h, 1.0, 1.0, 1.0, 1.0),
+        "lbm_set_outlet": capi.lbm_set_outlet(h, 0, 1.0),
+        "lbm_set_wall_distances": capi.lbm_set_wall_distances(h, None),
+        "lbm_set_inlet_cells": capi.lbm_set_inlet_cells(h, uin),
+        "lbm_init_fields": capi.lbm_init_fields(h, None, None),
+        "lbm_get_populations": capi.lbm_get_populations(h, pops),
+        "lbm_set_populations": capi.lbm_set_populations(h, pops),
+        "lbm_stats_enable": capi.lbm_stats_enable(h, 1),
+        "lbm_destroy": capi.lbm_destroy(h),
+    }
+    assert all(rc == capi.ERR_STATE for rc in state.values()), state
+    s = ctypes.c_int()
+    dp = ctypes.c_void_p()
+    assert capi.lbm_batch_admit(b.h, h, 5, ctypes.byref(s)) == capi.ERR_STATE
+    assert capi.lbm_batch_admit(b.h, other.h, 5, ctypes.byref(s)) == capi.ERR_ARG
+    assert capi.lbm_batch_admit(b.h, other.h, 0, ctypes.byref(s)) == capi.ERR_ARG
+    assert capi.lbm_batch_step(b.h, -1) == capi.ERR_ARG
+    assert capi.lbm_batch_release(b.h, slot, ctypes.byref(dp)) == capi.ERR_STATE
+    assert capi.lbm_batch_release(b.h, 999, ctypes.byref(dp)) == capi.ERR_ARG
+    assert capi.lbm_batch_destroy(b.h) == capi.ERR_STATE
+    b.step(10)
+    assert b.poll(wait=True) == [slot]
+    b.release(slot)
+    d.step(3)
+    d.destroy()
+    other.destroy()
+    b.destroy()
