@@ -157,3 +157,44 @@ def test_random_mix_packed_equals_alone(capi):
         assert np.array_equal(doms[k].populations(), alone[k]), f"case {k} differs"
         doms[k].destroy()
     b.destroy()
+
+
+@pytest.mark.parametrize("k", range(12))
+def test_random_configuration_statistics(capi, orc, k):
+    """Statistics (means of u, u_a u_b and the viscous stress over the
+    local-phase steps, FP32) under the random configurations, against the
+    same means over the oracle's pre-collision states.  Bounds: 5e-7 on u
+    and sigma, 5e-8 on u_a u_b, the FP32 rounding of the populations
+    (4e-7 per step) carried into the moments (measured at most 5.4e-8,
+    3.0e-9 and 4.2e-8)."""
+    c = make_case(k, "fp32")
+    fl = c["fl"]
+    steps = max(2, c["steps"])
+    say(f"statistics case {k}: shape {fl.shape} steps {steps} outlet {c['outlet']} curved {c['q'] is not None}")
+    d = build_domain(capi, c, "fp32")
+    d.stats_enable(True)
+    d.step(steps)
+    mu, muu, ms, n = d.stats()
+    d.destroy()
+    sampled = list(range(2, steps + 1, 2))
+    assert n == len(sampled)
+    rates = orc.rates_vector(c["omega"], c["omega_b"], order_rates=c["order"])
+    su, suu, ss = np.zeros((3,) + fl.shape), np.zeros((6,) + fl.shape), np.zeros((6,) + fl.shape)
+    pa, pb = [0, 1, 2, 0, 0, 1], [0, 1, 2, 1, 2, 2]
+    f = c["f0"]
+    for s in range(1, steps + 1):
+        if s in sampled:
+            pre = orc.stream(fl, f, periodic=c["periodic"], uin=c["uin"], outlet=c["outlet"], q=c["q"])
+            _, u = orc.moments(fl, pre)
+            su += u
+            for j in range(6):
+                suu[j] += u[pa[j]] * u[pb[j]]
+            ss += orc.stress(fl, pre, c["omega"])
+        st, f = orc.step(fl, f, rates, 1, periodic=c["periodic"], uin=c["uin"], outlet=c["outlet"], q=c["q"])
+        assert st == 0
+    upd = (fl == I.FLUID) | (fl == I.OUTLET)
+    eu = float(np.abs(mu - su / n)[:, upd].max())
+    euu = float(np.abs(muu - suu / n)[:, upd].max())
+    es = float(np.abs(ms - ss / n)[:, upd].max())
+    say(f"  max abs err u {eu:.2e}, uu {euu:.2e}, sigma {es:.2e}")
+    assert eu <= 5e-7 and euu <= 5e-8 and es <= 5e-7
