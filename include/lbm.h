@@ -327,7 +327,8 @@ int lbm_batch_admit(lbm_batch *b, lbm_domain *d, int n_steps, int *slot);
 
 /* Enqueue n packed steps (asynchronous; one graph replay per up to 8
  * steps).  A resident domain takes part in exactly its admitted number of
- * steps. */
+ * steps and ends bit for bit in the state lbm_step would give it alone,
+ * whatever it is packed with.  Errors: LBM_ERR_ARG for n < 0. */
 int lbm_batch_step(lbm_batch *b, int n);
 
 /*
