@@ -72,6 +72,8 @@ def lib():
         L.oracle_stress.argtypes = [u8p, ctypes.c_long, dp, ctypes.c_double, dp]
         L.oracle_set_outlet.argtypes = [ctypes.c_int, ctypes.c_double]
         L.oracle_set_wall_distances.argtypes = [dp]
+        L.oracle_set_equilibrium_order.argtypes = [ctypes.c_int]
+        L.oracle_set_equilibrium_order.restype = ctypes.c_int
         L.oracle_run_cells.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, dp, dp, dp,
                                        dp, ctypes.c_int, ctypes.c_long, lp, dp]
         L.oracle_run_cells.restype = ctypes.c_int
@@ -145,10 +147,13 @@ def cell_moments(f):
     return float(rho[0]), u
 
 
-def collide(f, rates):
-    """Sec. 2.1, Eq. (6) for one cell.  Returns (status, f*)."""
+def collide(f, rates, feq_order=6):
+    """Sec. 2.1, Eq. (6) for one cell, relaxing towards the equilibrium of
+    Eq. (4) truncated at feq_order (6: the paper's full expansion).
+    Returns (status, f*)."""
     out = np.zeros(NQ)
-    st = lib().oracle_collide(_dp(_f64(f)), _dp(_f64(rates)), _dp(out))
+    with _equilibrium(feq_order):
+        st = lib().oracle_collide(_dp(_f64(f)), _dp(_f64(rates)), _dp(out))
     return st, out
 
 
@@ -181,21 +186,23 @@ def stream(flags, f, periodic=0, uin=None, outlet=None, q=None):
     return g
 
 
-def collide_field(flags, f, rates):
+def collide_field(flags, f, rates, feq_order=6):
     fl, flp = _u8(flags)
     fa = _f64(f).copy()
-    st = lib().oracle_collide_field(flp, fl.size, _dp(_f64(rates)), _dp(fa))
+    with _equilibrium(feq_order):
+        st = lib().oracle_collide_field(flp, fl.size, _dp(_f64(rates)), _dp(fa))
     return st, fa
 
 
-def step(flags, f, rates, nsteps=1, periodic=0, uin=None, outlet=None, q=None):
-    """nsteps of stream + collide.  Returns (status, f_new)."""
+def step(flags, f, rates, nsteps=1, periodic=0, uin=None, outlet=None, q=None, feq_order=6):
+    """nsteps of stream + collide (feq_order: truncation of the equilibrium
+    the collision relaxes to, 6 the paper's).  Returns (status, f_new)."""
     fl, flp = _u8(flags)
     nz, ny, nx = fl.shape
     fa = _f64(f).copy()
     work = np.empty_like(fa)
     uin_a = _f64(uin)
-    with _boundary(flags, outlet, q):
+    with _boundary(flags, outlet, q), _equilibrium(feq_order):
         st = lib().oracle_step(flp, nx, ny, nz, periodic, _dp(uin_a), _dp(_f64(rates)), int(nsteps), _dp(fa),
                                _dp(work))
     return st, fa
@@ -239,6 +246,22 @@ class _boundary:
         lib().oracle_set_wall_distances(None)
 
 
+class _equilibrium:
+    """Selects the truncation order of the equilibrium the collision relaxes
+    to (Sec. 2.1, Eq. (4)) for the duration of one call; 6 is the paper's
+    full expansion and the default."""
+
+    def __init__(self, order):
+        self.order = int(order)
+
+    def __enter__(self):
+        if lib().oracle_set_equilibrium_order(self.order) != OK:
+            raise ValueError(f"equilibrium order {self.order} outside 2..6")
+
+    def __exit__(self, *exc):
+        lib().oracle_set_equilibrium_order(6)
+
+
 def stress(flags, f, omega):
     """Viscous stress sigma[6, nz, ny, nx] (xx, yy, zz, xy, xz, yz) of a
     pre-collision state (Sec. 2.2, Eq. (19); App. A, Eqs. (A.7)-(A.8)):
@@ -250,7 +273,8 @@ def stress(flags, f, omega):
     return sig
 
 
-def run_cells(flags, cells, rates, nsteps, periodic=0, uin=None, rho0=None, u0=None, outlet=None, q=None):
+def run_cells(flags, cells, rates, nsteps, periodic=0, uin=None, rho0=None, u0=None, outlet=None, q=None,
+              feq_order=6):
     """Populations after nsteps at the listed linear cell indices, starting
     from f^eq(rho0, u0); only the dependency cone is computed.  Returns
     (status, f[27, len(cells)])."""
@@ -258,7 +282,7 @@ def run_cells(flags, cells, rates, nsteps, periodic=0, uin=None, rho0=None, u0=N
     nz, ny, nx = fl.shape
     cl = np.ascontiguousarray(cells, dtype=np.int64)
     out = np.zeros((NQ, cl.size))
-    with _boundary(flags, outlet, q):
+    with _boundary(flags, outlet, q), _equilibrium(feq_order):
         st = lib().oracle_run_cells(flp, nx, ny, nz, periodic, _dp(_f64(uin)), _dp(_f64(rho0)), _dp(_f64(u0)),
                                     _dp(_f64(rates)), int(nsteps), cl.size,
                                     cl.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _dp(out))

@@ -311,10 +311,30 @@ void oracle_cell_moments(const double *f, double *rho, double *u)
         u[a] = j[a] / r;
 }
 
+/* Order N of the equilibrium the collision relaxes to (Sec. 2.1,
+ * Eq. (4): the Hermite expansion truncated at N).  6, the full expansion
+ * the stencil supports, is the paper's choice (App. A after Eq. (A.6));
+ * with N < 6 the central moments of f^eq are no longer (rho, 0, ..., 0),
+ * and the collision relaxes every moment towards those of the truncated
+ * f^eq (N = 2: the classical second-order equilibrium; N = 3 adds the
+ * third-order terms the paper mentions for Galilean invariance of the
+ * shear stress).  The initial state and the pressure outlet's ghost value
+ * keep the full expansion. */
+static int g_feq_order = 6;
+
+int oracle_set_equilibrium_order(int order)
+{
+    if (order < 2 || order > 6)
+        return O_ERR_ARG;
+    g_feq_order = order;
+    return O_OK;
+}
+
 /* Sec. 2.1, Eq. (6): the post-collision populations of one cell,
- * f* = f + T^-1 S T (f^eq - f), with f^eq the full sixth-order
- * expansion and T evaluated at the cell's own velocity.  Returns 0, or
- * O_ERR_UNSTABLE when rho <= 0 or a value is not finite. */
+ * f* = f + T^-1 S T (f^eq - f), with f^eq the expansion of order
+ * g_feq_order (the full sixth-order one by default) and T evaluated at
+ * the cell's own velocity.  Returns 0, or O_ERR_UNSTABLE when rho <= 0 or
+ * a value is not finite. */
 int oracle_collide(const double *f, const double *rates, double *fout)
 {
     oracle_init_tables();
@@ -325,7 +345,7 @@ int oracle_collide(const double *f, const double *rates, double *fout)
             fout[i] = f[i];
         return O_ERR_UNSTABLE;
     }
-    oracle_feq(rho, u, 6, feq);
+    oracle_feq(rho, u, g_feq_order, feq);
     oracle_transform(u, T);
     oracle_relaxation(rates, S);
     for (int i = 0; i < NQ; ++i)
@@ -701,16 +721,28 @@ int oracle_run_cells(const uint8_t *flags, int nx, int ny, int nz, unsigned peri
         if (list[k] < 0 || list[k] >= d.ncells || !updatable(flags[list[k]]))
             return O_ERR_ARG;
     /* need[t]: sorted cells whose state after step t is required */
+    int status = O_OK;
+    double *state = NULL;
     long **need = calloc((size_t)nsteps + 1, sizeof(long *));
     long *nneed = calloc((size_t)nsteps + 1, sizeof(long));
-    if (!need || !nneed)
-        return O_ERR_OOM;
+    if (!need || !nneed) {
+        status = O_ERR_OOM;
+        goto done;
+    }
     need[nsteps] = malloc(sizeof(long) * (size_t)nlist);
+    if (!need[nsteps]) {
+        status = O_ERR_OOM;
+        goto done;
+    }
     memcpy(need[nsteps], list, sizeof(long) * (size_t)nlist);
     nneed[nsteps] = unique_sorted(need[nsteps], nlist);
     for (int t = nsteps; t > 0; --t) {
         long cap = nneed[t] * NQ;
         long *prev = malloc(sizeof(long) * (size_t)cap);
+        if (!prev) {
+            status = O_ERR_OOM;
+            goto done;
+        }
         long m = 0;
         for (long k = 0; k < nneed[t]; ++k) {
             long cell = need[t][k];
@@ -726,7 +758,11 @@ int oracle_run_cells(const uint8_t *flags, int nx, int ny, int nz, unsigned peri
         need[t - 1] = prev;
     }
     /* state after step 0: the equilibrium of the initial fields */
-    double *state = malloc(sizeof(double) * NQ * (size_t)nneed[0]);
+    state = malloc(sizeof(double) * NQ * (size_t)nneed[0]);
+    if (!state) {
+        status = O_ERR_OOM;
+        goto done;
+    }
     for (long k = 0; k < nneed[0]; ++k) {
         long cell = need[0][k];
         double uu[3] = {0.0, 0.0, 0.0};
@@ -735,9 +771,12 @@ int oracle_run_cells(const uint8_t *flags, int nx, int ny, int nz, unsigned peri
                 uu[a] = u0[(long)a * d.ncells + cell];
         oracle_feq(rho0 ? rho0[cell] : 1.0, uu, 6, state + (long)NQ * k);
     }
-    int status = O_OK;
     for (int t = 1; t <= nsteps; ++t) {
         double *next = malloc(sizeof(double) * NQ * (size_t)nneed[t]);
+        if (!next) {
+            status = O_ERR_OOM;
+            goto done;
+        }
         const long *pc = need[t - 1];
         long npc = nneed[t - 1];
 #pragma omp parallel for schedule(dynamic, 64)
@@ -760,9 +799,11 @@ int oracle_run_cells(const uint8_t *flags, int nx, int ny, int nz, unsigned peri
         for (int i = 0; i < NQ; ++i)
             out[(long)i * nlist + k] = state[(long)NQ * slot + i];
     }
+done:
     free(state);
-    for (int t = 0; t <= nsteps; ++t)
-        free(need[t]);
+    if (need)
+        for (int t = 0; t <= nsteps; ++t)
+            free(need[t]);
     free(need);
     free(nneed);
     return status;
