@@ -187,6 +187,23 @@ int lbm_set_order_rates(lbm_domain *d, double omega3, double omega4, double omeg
 int lbm_set_outlet(lbm_domain *d, int kind, double rho_out);
 
 /*
+ * Order N of the equilibrium the collision relaxes to (Sec. 2.1, Eq. (4):
+ * the Hermite expansion summed to order N; App. A after Eq. (A.6)).
+ *   order  6 (the default and the paper's choice): the full expansion the
+ *          stencil supports, whose central moments are (rho, 0, ..., 0), so
+ *          the collision never forms f^eq.  2..5: the explicit truncated
+ *          equilibrium f^eq_N, formed per cell, and
+ *          f* = f^eq_N + T^-1 (I - S) T (f - f^eq_N); N = 2 is the classical
+ *          second-order equilibrium, N = 3 adds the third-order terms that
+ *          make the shear stress Galilean invariant.  Every rate applies as
+ *          with the full equilibrium.  The initial state (lbm_init_fields)
+ *          and the pressure outlet's ghost value keep the full expansion.
+ * Takes effect at the next step.  Errors: LBM_ERR_ARG for an order outside
+ * 2..6, LBM_ERR_STATE for a domain resident in a batch.
+ */
+int lbm_set_equilibrium_order(lbm_domain *d, int order);
+
+/*
  * Curved walls (Sec. 2.2: no-slip walls by the interpolated bounce-back of
  * Bouzidi, Firdaouss and Lallemand, linear form).
  *   q  host, 27*ncells floats, layout [i][cell], or NULL for the halfway
@@ -242,12 +259,37 @@ int lbm_init_fields(lbm_domain *d, const float *rho, const float *u);
 int lbm_step(lbm_domain *d, int n);
 
 /*
+ * Build the step graphs now (lbm_step builds them on first use after a
+ * change of rates, outlet, walls, statistics or equilibrium order): one
+ * graph per run length 64, 32, ..., 2 steps, each a chain of the step
+ * kernels.  Lets a caller keep the building out of a timed run.  Errors:
+ * LBM_ERR_STATE for a domain resident in a batch, LBM_ERR_DEVICE.
+ */
+int lbm_prepare_steps(lbm_domain *d);
+
+/*
  * Density and velocity of the stored state (equal to the pre-collision
  * moments of the same time level, since collision conserves them).
  *   rho  host, ncells floats; u host, 3*ncells floats [component][cell].
  * Cells that are not updated read rho = 0, u = 0.
  */
 int lbm_get_moments(lbm_domain *d, float *rho, float *u);
+
+/*
+ * As lbm_get_moments, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the moments are staged in a fixed device array of 64 MiB
+ * that the library holds on every device it runs on until the process
+ * ends, and no hipMalloc, hipFree or other allocating call is made.  The
+ * outputs and their layout are those of lbm_get_moments (host buffers of
+ * ncells and 3*ncells floats, caller-owned).  Domains of more than
+ * 4,194,304 cells (4 floats per cell) are refused with LBM_ERR_ARG.  Calls
+ * on one device share the array, which keeps the values of the last call;
+ * the library serialises them with a lock, so calls from several threads
+ * of one process do not overlap.  Errors: LBM_ERR_ARG, LBM_ERR_STATE for a
+ * domain resident in a batch, LBM_ERR_DEVICE.
+ */
+int lbm_get_moments_noalloc(lbm_domain *d, float *rho, float *u);
 
 /* As lbm_get_moments, into device buffers (ncells and 3*ncells floats). */
 int lbm_get_moments_device(lbm_domain *d, float *rho_dev, float *u_dev);
@@ -272,9 +314,9 @@ int lbm_set_populations(lbm_domain *d, const float *f);
  * every local-phase step (every second step) adds, for each updated cell,
  * u, u_a u_b and sigma_ab = 2 rho nu S_ab = -(1 - omega/2) M_ab of the
  * pre-collision state it collides (M_ab: central second-order Hermite
- * moment, omega the shear rate), summed in FP32 on the device
- * (15 * 64 * n_tiles floats).  Also accumulates while the domain is in a
- * batch.
+ * moment, omega the shear rate), summed in FP64 on the device
+ * (15 * 64 * n_tiles doubles; the products u_a u_b are formed in FP64 from
+ * the FP32 velocities).  Also accumulates while the domain is in a batch.
  * lbm_stats_enable(d, 1) clears the sums and starts; (d, 0) stops and keeps
  * them.
  */
@@ -282,15 +324,15 @@ int lbm_stats_enable(lbm_domain *d, int on);
 
 /*
  * Means of the statistics since the last lbm_stats_enable(d, 1).
- *   mean_u      host, 3*ncells floats [component][cell]
- *   mean_uu     host, 6*ncells floats: <u_x u_x>, <u_y u_y>, <u_z u_z>,
+ *   mean_u      host, 3*ncells doubles [component][cell]
+ *   mean_uu     host, 6*ncells doubles: <u_x u_x>, <u_y u_y>, <u_z u_z>,
  *               <u_x u_y>, <u_x u_z>, <u_y u_z> (Reynolds stress =
  *               <u_a u_b> - <u_a><u_b>)
- *   mean_sigma  host, 6*ncells floats, same component order
+ *   mean_sigma  host, 6*ncells doubles, same component order
  *   samples     number of samples in the means
  * Cells that are not updated read 0; all outputs are 0 without samples.
  */
-int lbm_stats_get(lbm_domain *d, float *mean_u, float *mean_uu, float *mean_sigma, uint64_t *samples);
+int lbm_stats_get(lbm_domain *d, double *mean_u, double *mean_uu, double *mean_sigma, uint64_t *samples);
 
 int lbm_domain_get_info(const lbm_domain *d, lbm_domain_info *info);
 
@@ -362,6 +404,12 @@ int lbm_batch_destroy(lbm_batch *b);
 /* Host-only self checks of the index arithmetic and tile classification
  * (no device call).  Returns LBM_OK or LBM_ERR_STATE with a message. */
 int lbm_selftest_host(void);
+
+/* Test hook for the error paths of batch admission: the n-th (n >= 1)
+ * table allocation or staged upload made by the batch calls from now on
+ * fails as if device memory were exhausted; n = 0 disables.  Returns
+ * LBM_ERR_ARG for n < 0. */
+int lbm_debug_fail_after(int n);
 
 /* Library version string. */
 const char *lbm_version(void);

@@ -43,6 +43,7 @@ class DomainInfo(ctypes.Structure):
 _vp = ctypes.c_void_p
 _ip = ctypes.POINTER(ctypes.c_int)
 _fp = ctypes.POINTER(ctypes.c_float)
+_dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 # name -> (restype, argtypes); the exported C ABI
@@ -60,13 +61,17 @@ SIGNATURES = {
     "lbm_set_inlet_cells": (ctypes.c_int, [_vp, _fp]),
     "lbm_init_fields": (ctypes.c_int, [_vp, _fp, _fp]),
     "lbm_step": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lbm_prepare_steps": (ctypes.c_int, [_vp]),
     "lbm_get_moments": (ctypes.c_int, [_vp, _fp, _fp]),
     "lbm_get_moments_device": (ctypes.c_int, [_vp, _vp, _vp]),
+    "lbm_get_moments_noalloc": (ctypes.c_int, [_vp, _fp, _fp]),
+    "lbm_set_equilibrium_order": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lbm_debug_fail_after": (ctypes.c_int, [ctypes.c_int]),
     "lbm_get_populations": (ctypes.c_int, [_vp, _fp]),
     "lbm_set_populations": (ctypes.c_int, [_vp, _fp]),
     "lbm_domain_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(DomainInfo)]),
     "lbm_stats_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
-    "lbm_stats_get": (ctypes.c_int, [_vp, _fp, _fp, _fp, ctypes.POINTER(ctypes.c_uint64)]),
+    "lbm_stats_get": (ctypes.c_int, [_vp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_uint64)]),
     "lbm_destroy": (ctypes.c_int, [_vp]),
     "lbm_last_error": (ctypes.c_char_p, []),
     "lbm_batch_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
@@ -157,6 +162,11 @@ class Domain:
     def set_order_rates(self, omega3, omega4, omega5, omega6):
         check(lbm_set_order_rates(self.h, omega3, omega4, omega5, omega6))
 
+    def set_equilibrium_order(self, order=6):
+        """Order of the equilibrium the collision relaxes to: 6 (full, the
+        paper's) or 2..5 (explicit truncated equilibrium)."""
+        check(lbm_set_equilibrium_order(self.h, int(order)))
+
     def set_outlet(self, kind="zero_gradient", rho_out=1.0):
         """Outlet condition: "zero_gradient" or "pressure" (rho_out)."""
         check(lbm_set_outlet(self.h, OUTLETS[kind], float(rho_out)))
@@ -186,6 +196,10 @@ class Domain:
     def step_status(self, n=1) -> int:
         return lbm_step(self.h, int(n))
 
+    def prepare_steps(self):
+        """Build the step graphs now (outside a timed run)."""
+        check(lbm_prepare_steps(self.h))
+
     def moments(self):
         rho = np.empty(self.shape, np.float32)
         u = np.empty((3,) + self.shape, np.float32)
@@ -209,11 +223,11 @@ class Domain:
 
     def stats(self):
         """(mean u [3,...], mean u_a u_b [6,...], mean sigma [6,...], samples)."""
-        mu = np.empty((3,) + self.shape, np.float32)
-        muu = np.empty((6,) + self.shape, np.float32)
-        ms = np.empty((6,) + self.shape, np.float32)
+        mu = np.empty((3,) + self.shape, np.float64)
+        muu = np.empty((6,) + self.shape, np.float64)
+        ms = np.empty((6,) + self.shape, np.float64)
         n = ctypes.c_uint64()
-        check(lbm_stats_get(self.h, mu.ctypes.data_as(_fp), muu.ctypes.data_as(_fp), ms.ctypes.data_as(_fp),
+        check(lbm_stats_get(self.h, mu.ctypes.data_as(_dp), muu.ctypes.data_as(_dp), ms.ctypes.data_as(_dp),
                             ctypes.byref(n)))
         return mu, muu, ms, int(n.value)
 

@@ -21,10 +21,24 @@
 #include <thread>
 #include <vector>
 
+#define LBM_HOST_TU
 #include "lbm_device.hpp"
+#include "lbm_instances.hpp"
 #include "../../include/lbm.h"
 
+// the step and state-access kernels are compiled per storage format in
+// lbm_kern.hip
+namespace lbm {
+LBM_INSTANCES(extern template, ST_FP32)
+LBM_INSTANCES(extern template, ST_FP16S)
+LBM_INSTANCES(extern template, ST_BF16S)
+} // namespace lbm
+
 using namespace lbm;
+
+// Read-back buffer of lbm_get_moments_noalloc (see scratch_address).
+constexpr uint64_t kScratchFloats = (uint64_t)16 << 20;
+static __device__ __align__(256) float scratch[kScratchFloats];
 
 namespace {
 
@@ -212,10 +226,10 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
     }
 }
 
-#ifndef LBM_GRAPH_STEPS
-#define LBM_GRAPH_STEPS 64
-#endif
-constexpr int kGraphSteps = LBM_GRAPH_STEPS; // steps per graph (even: ends in the phase it starts in)
+// Step graphs: one per length 64, 32, ..., 2 steps (even lengths end in the
+// phase they start in); a run of n steps replays the longest that fit.
+constexpr int kGraphSizes = 6;
+constexpr int graph_len(int j) { return 64 >> j; }
 
 // Bytes of a domain's population array: the tile blocks, then 2 x 9 side
 // rows of ny * nz elements, rounded up to 256 bytes.
@@ -241,7 +255,7 @@ struct lbm_domain {
     bool outlets = false; // the domain has outlet cells
     int outlet_kind = LBM_OUTLET_ZERO_GRADIENT;
     double rho_out = 1.0; // outlet density of the constant-pressure outlet
-    float *d_stats = nullptr;   // statistics sums, [15][64 ntiles]
+    double *d_stats = nullptr;  // statistics sums, [15][64 ntiles]
     bool stats_on = false;
     uint64_t stats_samples = 0; // local steps accumulated
     uint8_t *d_flags = nullptr;
@@ -258,16 +272,18 @@ struct lbm_domain {
     uint64_t ntiles = 0, nwall = 0, n_updated = 0;
     double omega = 1.0, omega_b = 1.0;
     double omega_o[4] = {1.0, 1.0, 1.0, 1.0}; // orders 3..6
+    int feq_order = 6;                        // 6: the full equilibrium; 2..5: explicit truncated one
     bool high1() const { return omega_o[0] == 1.0 && omega_o[1] == 1.0 && omega_o[2] == 1.0 && omega_o[3] == 1.0; }
     bool curved() const { return d_bzc != nullptr; }
+    bool explicit_feq() const { return feq_order < 6; }
     int variant() const
     {
-        return (high1() ? kVarH1 : 0) | (curved() ? kVarCurved : 0) |
+        return (explicit_feq() ? kVarFeq : (high1() ? kVarH1 : 0)) | (curved() ? kVarCurved : 0) |
                (outlet_kind == LBM_OUTLET_PRESSURE ? kVarPressure : 0);
     }
     bool unstable = false;
-    hipGraphExec_t graph = nullptr;
-    hipGraph_t graph_def = nullptr;
+    hipGraphExec_t graph[kGraphSizes] = {};   // graph j runs graph_len(j) steps from phase 0
+    hipGraph_t graph_def[kGraphSizes] = {};
     bool graph_dirty = true;
     std::vector<TileRec> h_tiles; // host copy of the tile list (batch tables are built from it)
     lbm_batch *batch = nullptr;    // resident in this batch
@@ -360,6 +376,7 @@ KDomain kdomain(const lbm_domain *d)
     k.outlet = d->outlet_kind == LBM_OUTLET_PRESSURE ? 1u : 0u;
     k.high1 = d->high1() ? 1u : 0u;
     k.rho_out = (float)d->rho_out;
+    k.feq_order = (uint32_t)d->feq_order;
     return k;
 }
 
@@ -402,12 +419,14 @@ int check_domain(const lbm_domain *d)
 
 void release_graph(lbm_domain *d)
 {
-    if (d->graph)
-        (void)hipGraphExecDestroy(d->graph);
-    if (d->graph_def)
-        (void)hipGraphDestroy(d->graph_def);
-    d->graph = nullptr;
-    d->graph_def = nullptr;
+    for (int j = 0; j < kGraphSizes; ++j) {
+        if (d->graph[j])
+            (void)hipGraphExecDestroy(d->graph[j]);
+        if (d->graph_def[j])
+            (void)hipGraphDestroy(d->graph_def[j]);
+        d->graph[j] = nullptr;
+        d->graph_def[j] = nullptr;
+    }
     d->graph_dirty = true;
 }
 
@@ -437,10 +456,12 @@ void free_domain(lbm_domain *d)
 
 // Calls fn(std::integral_constant<int, ST>, std::integral_constant<int, V>)
 // for a storage and a kernel variant known at run time.
+// The explicit equilibrium always takes the general collision, so a variant
+// with both bits set runs as the one without the reduced-collision bit.
 template <class Fn> decltype(auto) with_kernel(int storage, int v, Fn &&fn)
 {
     return dispatch_storage(storage, [&](auto st) {
-        switch (v) {
+        switch ((v & kVarFeq) ? (v & ~kVarH1) : v) {
         case 0:
             return fn(st, std::integral_constant<int, 0>{});
         case 1:
@@ -455,8 +476,16 @@ template <class Fn> decltype(auto) with_kernel(int storage, int v, Fn &&fn)
             return fn(st, std::integral_constant<int, 5>{});
         case 6:
             return fn(st, std::integral_constant<int, 6>{});
-        default:
+        case 7:
             return fn(st, std::integral_constant<int, 7>{});
+        case 8:
+            return fn(st, std::integral_constant<int, 8>{});
+        case 10:
+            return fn(st, std::integral_constant<int, 10>{});
+        case 12:
+            return fn(st, std::integral_constant<int, 12>{});
+        default:
+            return fn(st, std::integral_constant<int, 14>{});
         }
     });
 }
@@ -559,6 +588,37 @@ int init_eq(lbm_domain *d, const float *rho_dev, const float *u_dev)
 
 // Cells rounded up to whole 64-cell tiles.
 uint64_t plane_stride(uint64_t ncells) { return (ncells + 63) / 64 * 64; }
+
+// Read-back buffer of lbm_get_moments_noalloc, for callers that cannot
+// allocate: a fixed device array (64 MiB, 4 floats per cell) that each
+// device holds from the library's load to the end of the process.  Host
+// code uses it only through the device address hipGetSymbolAddress gives
+// for the current device, resolved once per device.  Calls on one device
+// share it, so they are serialised by a lock.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex[kMaxDevices];
+std::mutex g_scratch_resolve;
+float *g_scratch_ptr[kMaxDevices];
+
+int scratch_address(int device, float **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(LBM_ERR_DEVICE, "device %d out of range", device);
+    std::lock_guard<std::mutex> lock(g_scratch_resolve);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        HIP_TRY(hipGetDevice(&cur));
+        HIP_TRY(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(LBM_ERR_DEVICE, "read-back buffer address: %s", hipGetErrorString(e));
+        g_scratch_ptr[device] = (float *)p;
+    }
+    *out = g_scratch_ptr[device];
+    return LBM_OK;
+}
 
 int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int storage, void *hip_stream, void *fa,
            lbm_domain **out)
@@ -697,31 +757,33 @@ const void *step_kernel(int storage, int v, uint32_t phase, bool rows)
     });
 }
 
-// Build (not capture) a graph of kGraphSteps chained step nodes starting in
-// phase 0; built node by node so that work other threads issue meanwhile
-// cannot interfere.
+// Build (not capture) the step graphs: graph j chains graph_len(j) step
+// nodes starting in phase 0.  Built node by node so that work other threads
+// issue meanwhile cannot interfere.
 int build_graph(lbm_domain *d)
 {
     release_graph(d);
-    hipGraph_t g = nullptr;
-    HIP_TRY(hipGraphCreate(&g, 0));
     KDomain k = kdomain(d);
     const TileRec *tiles = d->d_tiles;
     uint32_t nt = (uint32_t)d->ntiles;
-    hipGraphNode_t prev = nullptr;
-    for (int s = 0; s < kGraphSteps; ++s) {
-        const void *fn = step_kernel(d->storage, d->variant(), (uint32_t)(s & 1), k.rowtiles != 0);
-        void *args[] = {&k, &tiles, &nt};
-        hipGraphNode_t node = nullptr;
-        hipError_t e = add_kernel_node(g, prev, fn, step_grid(d), kBlock, args, &node);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(g);
-            return fail(LBM_ERR_DEVICE, "graph node: %s", hipGetErrorString(e));
+    for (int j = 0; j < kGraphSizes; ++j) {
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipGraphCreate(&g, 0));
+        hipGraphNode_t prev = nullptr;
+        for (int s = 0; s < graph_len(j); ++s) {
+            const void *fn = step_kernel(d->storage, d->variant(), (uint32_t)(s & 1), k.rowtiles != 0);
+            void *args[] = {&k, &tiles, &nt};
+            hipGraphNode_t node = nullptr;
+            hipError_t e = add_kernel_node(g, prev, fn, step_grid(d), kBlock, args, &node);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(LBM_ERR_DEVICE, "graph node: %s", hipGetErrorString(e));
+            }
+            prev = node;
         }
-        prev = node;
+        d->graph_def[j] = g;
+        HIP_TRY(hipGraphInstantiate(&d->graph[j], g, nullptr, nullptr, 0));
     }
-    d->graph_def = g;
-    HIP_TRY(hipGraphInstantiate(&d->graph, g, nullptr, nullptr, 0));
     d->graph_dirty = false;
     return LBM_OK;
 }
@@ -788,6 +850,19 @@ int lbm_set_order_rates(lbm_domain *d, double omega3, double omega4, double omeg
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     for (int n = 0; n < 4; ++n)
         d->omega_o[n] = w[n];
+    d->graph_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_set_equilibrium_order(lbm_domain *d, int order)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (order < 2 || order > 6)
+        return fail(LBM_ERR_ARG, "equilibrium order %d outside 2..6", order);
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    d->feq_order = order;
     d->graph_dirty = true;
     return LBM_OK;
 }
@@ -980,6 +1055,9 @@ int lbm_step(lbm_domain *d, int n)
         return fail(LBM_ERR_UNSTABLE, "domain went unstable earlier; re-initialise it");
     if (d->ntiles == 0) // nothing is updated, the state stays as it is
         return LBM_OK;
+    if (n >= 2 && d->graph_dirty)
+        if (int rc = build_graph(d))
+            return rc;
     int left = n;
     uint64_t local_steps = 0;
     if (left > 0 && d->phase == 1) {
@@ -988,14 +1066,11 @@ int lbm_step(lbm_domain *d, int n)
         --left;
         ++local_steps;
     }
-    if (left >= kGraphSteps) {
-        if (d->graph_dirty)
-            if (int rc = build_graph(d))
-                return rc;
-        while (left >= kGraphSteps) {
-            HIP_TRY(hipGraphLaunch(d->graph, d->stream));
-            left -= kGraphSteps;
-            local_steps += kGraphSteps / 2;
+    for (int j = 0; j < kGraphSizes; ++j) {
+        while (left >= graph_len(j)) {
+            HIP_TRY(hipGraphLaunch(d->graph[j], d->stream));
+            left -= graph_len(j);
+            local_steps += (uint64_t)graph_len(j) / 2;
         }
     }
     while (left > 0) {
@@ -1010,6 +1085,17 @@ int lbm_step(lbm_domain *d, int n)
         return rc;
     if (d->unstable)
         return fail(LBM_ERR_UNSTABLE, "a step produced rho <= 0 or a non-finite value");
+    return LBM_OK;
+}
+
+int lbm_prepare_steps(lbm_domain *d)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    if (d->ntiles && d->graph_dirty)
+        return build_graph(d);
     return LBM_OK;
 }
 
@@ -1029,6 +1115,35 @@ int lbm_get_moments_device(lbm_domain *d, float *rho_dev, float *u_dev)
                            u_dev);
     });
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(d->stream));
+    return LBM_OK;
+}
+
+int lbm_get_moments_noalloc(lbm_domain *d, float *rho, float *u)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!rho || !u)
+        return fail(LBM_ERR_ARG, "null output");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    if (d->ncells > kScratchFloats / 4)
+        return fail(LBM_ERR_ARG, "domain of %llu cells exceeds the %llu cells of the static read-back buffer",
+                    (unsigned long long)d->ncells, (unsigned long long)(kScratchFloats / 4));
+    float *buf = nullptr;
+    if (int rc = scratch_address(d->device, &buf))
+        return rc;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex[d->device]);
+    HIP_TRY(normalise(d));
+    const KDomain k = kdomain(d);
+    const uint32_t blocks = (uint32_t)((d->ncells + 255) / 256);
+    dispatch_storage(d->storage, [&](auto st) {
+        hipLaunchKernelGGL((k_moments<decltype(st)::value>), dim3(blocks), dim3(256), 0, d->stream, k, buf,
+                           buf + d->ncells);
+    });
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(rho, buf, d->ncells * sizeof(float), hipMemcpyDeviceToHost, d->stream));
+    HIP_TRY(hipMemcpyAsync(u, buf + d->ncells, 3 * d->ncells * sizeof(float), hipMemcpyDeviceToHost, d->stream));
     HIP_TRY(hipStreamSynchronize(d->stream));
     return LBM_OK;
 }
@@ -1112,7 +1227,7 @@ int lbm_stats_enable(lbm_domain *d, int on)
     if (d->batch)
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     if (on) {
-        const size_t bytes = (size_t)15 * d->ntiles * 64 * sizeof(float);
+        const size_t bytes = (size_t)15 * d->ntiles * 64 * sizeof(double);
         if (!d->d_stats && bytes) {
             if (dalloc(d->stream, (void **)&d->d_stats, bytes) != hipSuccess)
                 return fail(LBM_ERR_OOM, "statistics sums (%zu bytes)", bytes);
@@ -1128,7 +1243,7 @@ int lbm_stats_enable(lbm_domain *d, int on)
     return LBM_OK;
 }
 
-int lbm_stats_get(lbm_domain *d, float *mean_u, float *mean_uu, float *mean_sigma, uint64_t *samples)
+int lbm_stats_get(lbm_domain *d, double *mean_u, double *mean_uu, double *mean_sigma, uint64_t *samples)
 {
     if (int rc = check_domain(d))
         return rc;
@@ -1138,25 +1253,25 @@ int lbm_stats_get(lbm_domain *d, float *mean_u, float *mean_uu, float *mean_sigm
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     *samples = d->stats_samples;
     const size_t n = d->ncells;
-    float *dout = nullptr;
-    if (dalloc(d->stream, (void **)&dout, 15 * n * sizeof(float)) != hipSuccess)
+    double *dout = nullptr;
+    if (dalloc(d->stream, (void **)&dout, 15 * n * sizeof(double)) != hipSuccess)
         return fail(LBM_ERR_OOM, "staging buffer");
     int rc = LBM_OK;
-    if (hipMemsetAsync(dout, 0, 15 * n * sizeof(float), d->stream) != hipSuccess)
+    if (hipMemsetAsync(dout, 0, 15 * n * sizeof(double), d->stream) != hipSuccess)
         rc = fail(LBM_ERR_DEVICE, "staging clear failed");
     if (rc == LBM_OK && d->d_stats && d->stats_samples && d->ntiles) {
         KDomain k = kdomain(d);
         k.stats = d->d_stats;
         const uint32_t blocks = (uint32_t)((d->ntiles + 3) / 4);
         hipLaunchKernelGGL(k_stats_export, dim3(blocks), dim3(256), 0, d->stream, k, (const TileRec *)d->d_tiles,
-                           (uint32_t)d->ntiles, (float)(1.0 / (double)d->stats_samples), dout);
+                           (uint32_t)d->ntiles, 1.0 / (double)d->stats_samples, dout);
         if (hipGetLastError() != hipSuccess)
             rc = fail(LBM_ERR_DEVICE, "statistics export failed");
     }
     if (rc == LBM_OK &&
-        (copy_sync(d->stream, mean_u, dout, 3 * n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
-         copy_sync(d->stream, mean_uu, dout + 3 * n, 6 * n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
-         copy_sync(d->stream, mean_sigma, dout + 9 * n, 6 * n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess))
+        (copy_sync(d->stream, mean_u, dout, 3 * n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+         copy_sync(d->stream, mean_uu, dout + 3 * n, 6 * n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+         copy_sync(d->stream, mean_sigma, dout + 9 * n, 6 * n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess))
         rc = fail(LBM_ERR_DEVICE, "statistics download failed");
     dfree(d->stream, dout);
     return rc;

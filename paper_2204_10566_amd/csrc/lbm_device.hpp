@@ -47,9 +47,11 @@ constexpr uint32_t kMaskSkip = 1u << 31;
 
 // Step-kernel variants: bit 0 -- every rate of order >= 3 is 1 (the
 // reduced collision); bit 1 -- curved walls (interpolated bounce-back);
-// bit 2 -- constant-pressure outlet.  Domains without an option run
-// kernels compiled without its code (fewer registers, more waves).
-constexpr int kVarH1 = 1, kVarCurved = 2, kVarPressure = 4, kVariants = 8;
+// bit 2 -- constant-pressure outlet; bit 3 -- explicit equilibrium
+// truncated below the full expansion (never with bit 0).  Domains without
+// an option run kernels compiled without its code (fewer registers, more
+// waves).
+constexpr int kVarH1 = 1, kVarCurved = 2, kVarPressure = 4, kVarFeq = 8, kVariants = 16;
 // inlet record of a cell with moving-wall inlet links: word 0 the link mask,
 // word 1 + i the ordinal of the inlet cell that link i comes from
 constexpr uint32_t kRecWords = 28;
@@ -99,7 +101,7 @@ struct KDomain {
     uint32_t periodic;
     float omega, omega_b;
     float omega_o[4];        // rates of the central moments of order 3, 4, 5, 6
-    float *stats;            // statistics sums [15][sstride] (see local_finish), or null
+    double *stats;           // statistics sums [15][sstride] (see local_finish), or null
     uint32_t sstride;        // 64 x number of tiles
     // batched execution: the domain takes part in global steps
     // [step0, step0 + nsteps), starting in phase ph0.
@@ -111,6 +113,7 @@ struct KDomain {
     float *bzaux;            // f*_k of the lanes' previous step, [27][64] per wall tile
     uint32_t rowtiles;       // nx / 64 when nx is a multiple of 64 (stream_tile_rows), else 0
     FastDiv drow;            // division by rowtiles
+    uint32_t feq_order;      // 2..5: explicit equilibrium truncated at that order (variant kVarFeq); 6: full
 };
 
 // One entry of a tile list (40 bytes; a wave reads it with scalar loads).
@@ -322,14 +325,10 @@ __device__ __forceinline__ float collide_h1(float (&f)[Q], float omega, float om
     return rho;
 }
 
-// Forward central-Hermite transform and relaxation for general rates of the
-// orders 3..6 (the order of moment slot a + 3b + 9c is a + b + c):
-// three sweeps of the 1-D map (x raw, then shifted to the central moments
-// about ux; y and z directly central), then the relaxation.
-__device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float omega_b, const float (&omega_o)[4],
-                                               float &ux, float &uy, float &uz, float (&m2)[6])
+// Raw x sweep: per (c_y, c_z) row t = b + 3 c, slots 3t, 3t+1, 3t+2 take
+// the zeroth, first and second raw moments in x of the row.
+__device__ __forceinline__ void x_sweep_raw(float (&f)[Q])
 {
-    // x sweep, raw: s0 = sum, s1 = first moment, s2 = second moment
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         const float A = f[3 * t], B = f[3 * t + 1], C = f[3 * t + 2];
@@ -337,23 +336,12 @@ __device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float
         f[3 * t + 1] = C - A;
         f[3 * t + 2] = C + A;
     }
-    float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        rho += f[3 * t];
-        jx += f[3 * t + 1];
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-        jy += f[3 * (3 * c + 2)] - f[3 * (3 * c + 0)];
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-        jz += f[3 * (b + 6)] - f[3 * b];
-    const float inv = __builtin_amdgcn_rcpf(rho);
-    ux = jx * inv;
-    uy = jy * inv;
-    uz = jz * inv;
-    // x sweep, shift to central moments about ux
+}
+
+// From the raw x sweep to the central Hermite moments about (ux, uy, uz):
+// the x moments shifted to central ones, then the y and z sweeps.
+__device__ __forceinline__ void central_sweeps(float (&f)[Q], float ux, float uy, float uz)
+{
     {
         const float k2 = ux * ux - kTheta0, tu = 2.f * ux;
 #pragma unroll
@@ -363,7 +351,6 @@ __device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float
             f[3 * t + 2] = __builtin_fmaf(k2, s0, __builtin_fmaf(-tu, s1, s2));
         }
     }
-    // y and z sweeps
 #define LBM_FWD_SWEEP(U, STRIDE, OUTER)                                                                          \
     {                                                                                                            \
         const float k2 = U * U - kTheta0, tu = 2.f * U;                                                          \
@@ -381,10 +368,17 @@ __device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float
 #define LBM_OUTER_Z(t) (t)
     LBM_FWD_SWEEP(uy, 3, LBM_OUTER_Y)
     LBM_FWD_SWEEP(uz, 9, LBM_OUTER_Z)
+#undef LBM_FWD_SWEEP
+}
 
-    // relaxation (Sec. 2.1 after Eq. (8); App. A after Eq. (A.6)):
-    // order 0 and 1 conserved; second order: deviator and off-diagonal at
-    // omega, trace at omega_b; order n >= 3 at omega_o[n - 3].
+// Relaxation of the central moments (Sec. 2.1 after Eq. (8); App. A after
+// Eq. (A.6)): order 0 and 1 kept; second order: deviator and off-diagonal
+// scaled by 1 - omega, trace by 1 - omega_b; order n >= 3 (slot a + 3b + 9c
+// has order a + b + c) by 1 - omega_o[n - 3].  m2 receives the six
+// second-order moments before relaxation (xx, yy, zz, xy, xz, yz).
+__device__ __forceinline__ void relax_moments(float (&f)[Q], float omega, float omega_b, const float (&omega_o)[4],
+                                              float (&m2)[6])
+{
     m2[0] = f[2];
     m2[1] = f[6];
     m2[2] = f[18];
@@ -408,18 +402,41 @@ __device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float
         if (n >= 3)
             f[k] *= 1.f - omega_o[n - 3];
     }
+}
+
+// Forward central-Hermite transform and relaxation for general rates of the
+// orders 3..6: the raw x sweep gives rho and u, then the central sweeps
+// and the relaxation.
+__device__ __forceinline__ float moments_relax(float (&f)[Q], float omega, float omega_b, const float (&omega_o)[4],
+                                               float &ux, float &uy, float &uz, float (&m2)[6])
+{
+    x_sweep_raw(f);
+    float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        rho += f[3 * t];
+        jx += f[3 * t + 1];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        jy += f[3 * (3 * c + 2)] - f[3 * (3 * c + 0)];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        jz += f[3 * (b + 6)] - f[3 * b];
+    const float inv = __builtin_amdgcn_rcpf(rho);
+    ux = jx * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+    central_sweeps(f, ux, uy, uz);
+    relax_moments(f, omega, omega_b, omega_o, m2);
     return rho;
 }
 
-template <bool HIGH1>
-__device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega_b, const float (&omega_o)[4],
-                                         float &ux, float &uy, float &uz, float (&m2)[6])
+// Inverse sweeps z, y, x: raw moments R0 = m0, R1 = m1 + u m0,
+// R2 = m2 + 2 u m1 + (u^2 + theta0) m0; then f(+1) = (R2 + R1)/2,
+// f(-1) = (R2 - R1)/2, f(0) = R0 - R2.
+__device__ __forceinline__ void inverse_sweeps(float (&f)[Q], float ux, float uy, float uz)
 {
-    const float rho = HIGH1 ? collide_h1(f, omega, omega_b, ux, uy, uz, m2)
-                            : moments_relax(f, omega, omega_b, omega_o, ux, uy, uz, m2);
-    // inverse sweeps z, y, x: raw moments R0 = m0, R1 = m1 + u m0,
-    // R2 = m2 + 2 u m1 + (u^2 + theta0) m0; then f(+1) = (R2 + R1)/2,
-    // f(-1) = (R2 - R1)/2, f(0) = R0 - R2.
 #define LBM_INV_SWEEP(U, STRIDE, OUTER)                                                                          \
     {                                                                                                            \
         const float k2 = U * U + kTheta0, tu = 2.f * U;                                                          \
@@ -438,11 +455,123 @@ __device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega
     LBM_INV_SWEEP(uz, 9, LBM_OUTER_Z)
     LBM_INV_SWEEP(uy, 3, LBM_OUTER_Y)
     LBM_INV_SWEEP(ux, 1, LBM_OUTER_X)
-#undef LBM_FWD_SWEEP
 #undef LBM_INV_SWEEP
 #undef LBM_OUTER_X
 #undef LBM_OUTER_Y
 #undef LBM_OUTER_Z
+}
+
+template <bool HIGH1>
+__device__ __forceinline__ float collide(float (&f)[Q], float omega, float omega_b, const float (&omega_o)[4],
+                                         float &ux, float &uy, float &uz, float (&m2)[6])
+{
+    const float rho = HIGH1 ? collide_h1(f, omega, omega_b, ux, uy, uz, m2)
+                            : moments_relax(f, omega, omega_b, omega_o, ux, uy, uz, m2);
+    inverse_sweeps(f, ux, uy, uz);
+    return rho;
+}
+
+// The equilibrium of Eq. (4) truncated at order N (2 <= N <= 6), at every
+// population.  With the per-axis Hermite terms (App. A, Eqs. (A.3)-(A.4))
+// e_0 = 1, e_1(c, v) = c v / theta0, e_2(c, v) = (c^2 - theta0) v^2 /
+// (2 theta0^2), the term of the expansion with n_a factors of axis a is
+// rho w_i prod_a e_{n_a}(c_ia, u_a) (a tensor with axis a repeated n_a times
+// appears n! / prod n_a! times in the sum over index tuples); the order of
+// the term is n_x + n_y + n_z.  So f^eq_N is rho w_i times the sum of the
+// coefficients of t^0 .. t^N of prod_a (1 + e_1 t + e_2 t^2).
+__device__ __forceinline__ void feq_truncated(float rho, float ux, float uy, float uz, uint32_t N, float (&fe)[Q])
+{
+    // per axis and c = -1, 0, +1: (e_1, e_2)
+    const float vx2 = ux * ux, vy2 = uy * uy, vz2 = uz * uz;
+    const float e1x[3] = {-3.f * ux, 0.f, 3.f * ux}, e2x[3] = {3.f * vx2, -1.5f * vx2, 3.f * vx2};
+    const float e1y[3] = {-3.f * uy, 0.f, 3.f * uy}, e2y[3] = {3.f * vy2, -1.5f * vy2, 3.f * vy2};
+    const float e1z[3] = {-3.f * uz, 0.f, 3.f * uz}, e2z[3] = {3.f * vz2, -1.5f * vz2, 3.f * vz2};
+    const float k3 = N >= 3u ? 1.f : 0.f, k4 = N >= 4u ? 1.f : 0.f, k5 = N >= 5u ? 1.f : 0.f,
+                k6 = N >= 6u ? 1.f : 0.f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // x times y: coefficients of t^1 .. t^4
+            const float p1 = e1x[a] + e1y[b];
+            const float p2 = e2x[a] + e1x[a] * e1y[b] + e2y[b];
+            const float p3 = e2x[a] * e1y[b] + e1x[a] * e2y[b];
+            const float p4 = e2x[a] * e2y[b];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float q1 = p1 + e1z[c];
+                const float q2 = p2 + p1 * e1z[c] + e2z[c];
+                const float q3 = p3 + p2 * e1z[c] + p1 * e2z[c];
+                const float q4 = p4 + p3 * e1z[c] + p2 * e2z[c];
+                const float q5 = p4 * e1z[c] + p3 * e2z[c];
+                const float q6 = p4 * e2z[c];
+                const float sum = 1.f + q1 + q2 + k3 * q3 + k4 * q4 + k5 * q5 + k6 * q6;
+                const int i = a + 3 * b + 9 * c;
+                fe[i] = rho * weight(i) * sum;
+            }
+        }
+}
+
+// Collision towards the explicit truncated equilibrium (Sec. 2.1, Eqs. (4)
+// and (6) with the expansion summed to order N < 6): with g = f - f^eq_N,
+// f* = f + T^-1 S T (f^eq_N - f) = f^eq_N + T^-1 (I - S) T g.  T g is the
+// forward transform about the cell's velocity (its orders 0 and 1 vanish up
+// to rounding; orders >= 3 no longer do, unlike with the full expansion);
+// the relaxation and the inverse are those of the implicit form.
+__device__ __forceinline__ float collide_feq(float (&f)[Q], float omega, float omega_b, const float (&omega_o)[4],
+                                             uint32_t N, float &ux, float &uy, float &uz, float (&m2)[6])
+{
+    float s0[9], s1[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        s0[t] = f[3 * t] + f[3 * t + 1] + f[3 * t + 2];
+        s1[t] = f[3 * t + 2] - f[3 * t];
+    }
+    float rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        rho += s0[t];
+        jx += s1[t];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        jy += s0[2 + 3 * c] - s0[3 * c];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+        jz += s0[b + 6] - s0[b];
+    const float inv = __builtin_amdgcn_rcpf(rho);
+    ux = jx * inv;
+    uy = jy * inv;
+    uz = jz * inv;
+    // The opaque copies below fix the rounding of every value that meets
+    // f^eq_N: without them the compiler may fuse a product into the
+    // neighbouring add in one kernel and not in another (packed launches
+    // inline this next to the other collisions), and a domain would no
+    // longer end bit for bit where it ends alone.
+    {
+        float fe[Q];
+        feq_truncated(rho, ux, uy, uz, N, fe);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            asm volatile("" : "+v"(fe[k]));
+            f[k] -= fe[k];
+        }
+    }
+    x_sweep_raw(f);
+    central_sweeps(f, ux, uy, uz);
+    relax_moments(f, omega, omega_b, omega_o, m2);
+    inverse_sweeps(f, ux, uy, uz);
+    // f^eq_N again (recomputed rather than held through the transform; the
+    // opaque copy keeps the compiler from reusing the first evaluation)
+    float r2 = rho;
+    asm volatile("" : "+v"(r2) : "v"(f[0]), "v"(f[26]));
+    float fe[Q];
+    feq_truncated(r2, ux, uy, uz, N, fe);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        asm volatile("" : "+v"(fe[k]), "+v"(f[k]));
+        f[k] += fe[k];
+    }
     return rho;
 }
 
@@ -455,7 +584,17 @@ template <int V, bool DYN>
 __device__ __forceinline__ float collide_lane(const KDomain &d, float (&f)[Q], float &ux, float &uy, float &uz,
                                               float (&m2)[6])
 {
-    if constexpr ((V & kVarH1) != 0) {
+    if constexpr ((V & kVarFeq) != 0) {
+        if constexpr (DYN) {
+            // a packed domain with the full equilibrium takes its own path
+            if (d.feq_order >= 6u) {
+                if (d.high1)
+                    return collide<true>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+                return collide<false>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
+            }
+        }
+        return collide_feq(f, d.omega, d.omega_b, d.omega_o, d.feq_order, ux, uy, uz, m2);
+    } else if constexpr ((V & kVarH1) != 0) {
         return collide<true>(f, d.omega, d.omega_b, d.omega_o, ux, uy, uz, m2);
     } else if constexpr (DYN) {
         if (d.high1)
@@ -944,7 +1083,10 @@ __device__ __forceinline__ void local_load(const KDomain &d, const TileRec &rec,
 // and the viscous stress sigma_ab = 2 rho nu S_ab = -(1 - omega/2) M_ab from
 // the central second-order Hermite moments M_ab (Sec. 2.2, Eqs. (15)-(19);
 // App. A, Eqs. (A.7)-(A.8)); sums of component c at stats[c * sstride +
-// 64 ord + lane].
+// 64 ord + lane].  The sums are FP64 and the products u_a u_b are formed
+// exactly in FP64 from the FP32 velocities, so that averages over long
+// windows keep their digits and the Reynolds stress <u_a u_b> - <u_a><u_b>
+// does not cancel away.
 template <int ST, int V, bool DYN = false>
 __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &rec, uint32_t lane, float (&f)[Q])
 {
@@ -970,10 +1112,11 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
     for (int k = 0; k < Q; ++k)
         S::store(r, self, pop_bytes<es>(Q - 1 - k), f[k], k);
     if (d.stats) {
-        float *acc = d.stats + rec.ord * 64u + lane;
+        double *acc = d.stats + rec.ord * 64u + lane;
         const float ks = -(1.f - 0.5f * d.omega);
-        const float v[15] = {ux, uy, uz, ux * ux, uy * uy, uz * uz, ux * uy, ux * uz, uy * uz,
-                             ks * m2[0], ks * m2[1], ks * m2[2], ks * m2[3], ks * m2[4], ks * m2[5]};
+        const double vx = ux, vy = uy, vz = uz;
+        const double v[15] = {vx, vy, vz, vx * vx, vy * vy, vz * vz, vx * vy, vx * vz, vy * vz,
+                              ks * m2[0], ks * m2[1], ks * m2[2], ks * m2[3], ks * m2[4], ks * m2[5]};
 #pragma unroll
         for (int c = 0; c < 15; ++c)
             acc[(size_t)c * d.sstride] += v[c];
@@ -1002,6 +1145,11 @@ __device__ __forceinline__ void local_tile(const KDomain &d, const TileRec &rec,
     local_load<ST>(d, rec, lane, f);
     local_finish<ST, V, DYN>(d, rec, lane, f);
 }
+
+#ifdef LBM_HOST_TU
+// (The kernels that are not templates are defined in the library's host
+// translation unit only; the templates are instantiated per storage in
+// their own translation units.)
 
 // Inlet terms of the inlet tiles: for inlet link i of a cell, the moving-
 // wall term 2 w_i (c_i . u_in) / theta0 with wall density 1 and u_in at the
@@ -1035,6 +1183,8 @@ __global__ __launch_bounds__(256) void k_inlet_terms(const TileRec *__restrict__
         out[i * 64] = v;
     }
 }
+
+#endif // LBM_HOST_TU
 
 // Block index -> logical block: consecutive hardware blocks go round-robin
 // to the 8 XCDs; give each XCD a contiguous range of tiles so that the cache
@@ -1120,11 +1270,13 @@ __global__ __launch_bounds__(kBlock) void k_collide_batched(const KDomain *__res
     }
 }
 
+#ifdef LBM_HOST_TU
 __global__ void k_advance_step(uint32_t *ctrl, uint32_t by)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0)
         ctrl[1] = ctrl[1] + by;
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // State access.  Outside a step the host keeps a domain in phase 0, where
@@ -1313,11 +1465,12 @@ __global__ __launch_bounds__(256) void k_moments(KDomain d, float *__restrict__ 
     u[2u * d.ncells + c] = jz;
 }
 
+#ifdef LBM_HOST_TU
 // Means of the statistics sums (scale = 1 / samples) to [component][cell]
 // arrays (3 for u, 6 for u_a u_b, 6 for sigma); cells that are not updated
 // are left as they are (the host zeroes the outputs).  One wave per tile.
 __global__ __launch_bounds__(256) void k_stats_export(KDomain d, const TileRec *__restrict__ tiles, uint32_t ntiles,
-                                                      float scale, float *__restrict__ out)
+                                                      double scale, double *__restrict__ out)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + (threadIdx.x >> 6));
@@ -1332,6 +1485,8 @@ __global__ __launch_bounds__(256) void k_stats_export(KDomain d, const TileRec *
     for (int c = 0; c < 15; ++c)
         out[(size_t)c * d.ncells + cell] = d.stats[(size_t)c * d.sstride + rec.ord * 64u + lane] * scale;
 }
+
+#endif // LBM_HOST_TU
 
 // Phase-0 state <-> FP32 values of f_i, layout [i][cell] without padding.
 template <int ST>

@@ -162,7 +162,8 @@ def test_random_mix_packed_equals_alone(capi):
 @pytest.mark.parametrize("k", range(12))
 def test_random_configuration_statistics(capi, orc, k):
     """Statistics (means of u, u_a u_b and the viscous stress over the
-    local-phase steps, FP32) under the random configurations, against the
+    local-phase steps, FP64 sums of FP32 moments) under the random
+    configurations, against the
     same means over the oracle's pre-collision states.  Bounds: 5e-7 on u
     and sigma, 5e-8 on u_a u_b, the FP32 rounding of the populations
     (4e-7 per step) carried into the moments (measured at most 5.4e-8,
