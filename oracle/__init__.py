@@ -21,7 +21,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
-_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+# LBM_ORACLE_LIBRARY selects another build of the same source (the
+# sanitizer test loads an AddressSanitizer/UBSan build through it)
+_LIB = os.environ.get("LBM_ORACLE_LIBRARY") or os.path.join(_HERE, "liblbm_oracle.so")
 
 NQ = 27
 THETA0 = 1.0 / 3.0
