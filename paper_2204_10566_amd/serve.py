@@ -69,6 +69,19 @@ def prepare(req: I.Request, storage: str, stream=None) -> capi.Domain:
     return d
 
 
+def estimate_device_bytes(req: I.Request, storage: str) -> int:
+    """Device memory a request will hold once prepared, before it is: its
+    population array plus at most 12 bytes per cell of tables (flags, tile
+    records, link masks and inlet data of the wall tiles)."""
+    nz = req.nozzle
+    st = capi.STORAGE[storage]
+    return int(capi.lbm_array_bytes(nz.length, nz.n, nz.n, st)) + 12 * req.ncells
+
+
+def _failed_code(exc: BaseException) -> int:
+    return exc.code if isinstance(exc, capi.LbmError) else capi.ERR_DEVICE
+
+
 def finish(d: capi.Domain, keep_fields: bool):
     """Copy the result to the host and free the domain.  Returns (status, rho,
     u, updated cells); status is LBM_ERR_UNSTABLE if any step went unstable."""
@@ -126,7 +139,15 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
     None or 0, by the number of updated cells resident at once (a request
     larger than the cap is still admitted when nothing else is resident).
     order: "fifo" admits in arrival order, "sjf" admits the waiting request
-    with the least work (updated cells x steps) first."""
+    with the least work (updated cells x steps) first.
+
+    Every byte of device memory the service holds counts against the
+    budget: a request is prepared (its domain created on the device) only
+    while the resident domains, the prepared ones waiting for admission and
+    those being prepared (at an upper estimate) leave room for it; until
+    then it waits as a host-side description.  A request that can never fit
+    the budget, or whose preparation fails, is answered at once with the
+    error code as its status; the service goes on."""
     import torch
 
     if budget_bytes is None:
@@ -137,37 +158,72 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
     reqs = sorted(trace, key=lambda r: r.arrival)
     outs = {r.rid: Outcome(r.rid, r.arrival, steps=r.steps) for r in reqs}
     nxt = 0
-    preparing = collections.deque()  # (req, future) in arrival order
-    waiting = collections.deque()    # (req, domain) prepared, not yet admitted
-    resident = {}                    # slot -> (req, domain, updated cells)
+    arrived = collections.deque()    # requests that arrived, not yet being prepared
+    preparing = collections.deque()  # (req, future, estimated bytes) in arrival order
+    prep_bytes = 0                   # estimates of the requests being prepared
+    waiting = collections.deque()    # (req, domain, cells, bytes) prepared, not yet admitted
+    wait_bytes = 0                   # device bytes of the prepared, waiting domains
+    resident = {}                    # slot -> (req, domain, updated cells, device bytes)
     resident_cells = 0
     peak_cells = 0                   # most updated cells resident at once
     idle_ticks = 0                   # loop turns with nothing resident
-    finishing = []                   # (req, future)
+    finishing = []                   # (req, future, device bytes)
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0
     remaining = len(reqs)
+    fin_bytes = 0                    # device bytes of released domains not yet read back and freed
+    peak_held = 0                    # most device bytes held at once (resident, released, waiting, preparing)
+
+    def fail_request(r, code):
+        nonlocal remaining
+        o = outs[r.rid]
+        o.done, o.status = now(), code
+        remaining -= 1
+
     try:
         while remaining:
             t = now()
             while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= t):
-                preparing.append((reqs[nxt], pool.submit(prepare, reqs[nxt], storage)))
+                arrived.append(reqs[nxt])
                 nxt += 1
+            # prepare arrived requests in order while the budget has room
+            while arrived:
+                r = arrived[0]
+                est = estimate_device_bytes(r, storage)
+                if est > budget_bytes:
+                    arrived.popleft()
+                    fail_request(r, capi.ERR_OOM)
+                    continue
+                in_use = batch.stats()[3]
+                if in_use + fin_bytes + wait_bytes + prep_bytes + est > budget_bytes:
+                    break
+                arrived.popleft()
+                preparing.append((r, pool.submit(prepare, r, storage), est))
+                prep_bytes += est
+                peak_held = max(peak_held, in_use + fin_bytes + wait_bytes + prep_bytes)
             while preparing and preparing[0][1].done():
-                r, fut = preparing.popleft()
-                d = fut.result()
-                waiting.append((r, d, int(d.info().n_updated)))
+                r, fut, est = preparing.popleft()
+                prep_bytes -= est
+                try:
+                    d = fut.result()
+                except Exception as exc:  # the request fails, the service goes on
+                    fail_request(r, _failed_code(exc))
+                    continue
+                info = d.info()
+                waiting.append((r, d, int(info.n_updated), int(info.device_bytes)))
+                wait_bytes += int(info.device_bytes)
             if order == "sjf" and len(waiting) > 1:
                 waiting = collections.deque(sorted(waiting, key=lambda e: e[2] * e[0].steps))
             while waiting:
-                r, d, nupd = waiting[0]
+                r, d, nupd, nbytes = waiting[0]
                 if work_cap_cells and resident and resident_cells + nupd > work_cap_cells:
                     break
                 slot = batch.admit(d, r.steps)
                 if slot is None:
                     break
                 waiting.popleft()
-                resident[slot] = (r, d, nupd)
+                wait_bytes -= nbytes
+                resident[slot] = (r, d, nupd, nbytes)
                 resident_cells += nupd
                 peak_cells = max(peak_cells, resident_cells)
                 outs[r.rid].admitted = now()
@@ -177,19 +233,25 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
             elif not resident:
                 idle_ticks += 1
             for slot in batch.poll():
-                r, d, nupd = resident.pop(slot)
+                r, d, nupd, nbytes = resident.pop(slot)
                 resident_cells -= nupd
                 batch.release(slot)
-                finishing.append((r, pool.submit(finish, d, keep_fields)))
+                fin_bytes += nbytes
+                finishing.append((r, pool.submit(finish, d, keep_fields), nbytes))
             still = []
-            for r, fut in finishing:
+            for r, fut, nbytes in finishing:
                 if fut.done():
-                    st, rho, u, nupd = fut.result()
+                    fin_bytes -= nbytes
+                    try:
+                        st, rho, u, nupd = fut.result()
+                    except Exception as exc:
+                        fail_request(r, _failed_code(exc))
+                        continue
                     o = outs[r.rid]
                     o.done, o.status, o.rho, o.u, o.updated_cells = now(), st, rho, u, nupd
                     remaining -= 1
                 else:
-                    still.append((r, fut))
+                    still.append((r, fut, nbytes))
             finishing = still
             if not resident or enq - done >= max_ahead * steps_per_tick:
                 time.sleep(2e-4)
@@ -201,6 +263,7 @@ def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8
     s = summarise("continuous-batching", res, wall, budget_bytes)
     s["work_cap_cells"] = work_cap_cells
     s["peak_resident_cells"] = peak_cells
+    s["peak_held_bytes"] = peak_held
     s["order"] = order
     s["idle_loop_turns"] = idle_ticks
     return res, s
@@ -223,7 +286,11 @@ def serve_serial(trace, storage="fp16s", workers=4, keep_fields=False, realtime=
             while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= now()):
                 futures[reqs[nxt].rid] = pool.submit(prepare, reqs[nxt], storage)
                 nxt += 1
-            d = futures.pop(r.rid).result()
+            try:
+                d = futures.pop(r.rid).result()
+            except Exception as exc:  # the request fails, the service goes on
+                outs.append(Outcome(r.rid, r.arrival, steps=r.steps, done=now(), status=_failed_code(exc)))
+                continue
             o = Outcome(r.rid, r.arrival, steps=r.steps, admitted=now())
             st = d.step_status(r.steps)
             st2, o.rho, o.u, o.updated_cells = finish(d, keep_fields)

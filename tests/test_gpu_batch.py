@@ -155,10 +155,94 @@ def test_serving_alone_equals_mix(capi):
                                         keep_fields=True, realtime=False)
     alone, s_alone = serve.serve_serial(tr, storage="fp16s", keep_fields=True, realtime=False)
     say(f"  {s_mix}\n  {s_alone}")
+    # the requests were resident together: more updated cells at once than
+    # the largest request alone
+    assert s_mix["peak_resident_cells"] > max(o.updated_cells for o in alone)
     by = {o.rid: o for o in alone}
     for o in mix:
         a = by[o.rid]
         assert o.status == a.status
+        assert np.array_equal(o.rho, a.rho) and np.array_equal(o.u, a.u), f"request {o.rid} differs"
+
+
+def test_admission_failure_leaves_batch_consistent(capi):
+    """An allocation or upload that fails during admission (forced from the
+    host with lbm_debug_fail_after, at each fallible step in turn, including
+    a table growth) returns LBM_ERR_OOM, leaves the domain stand-alone and
+    the batch working: the domain is admitted again afterwards, and every
+    domain ends bit for bit where it ends alone."""
+    specs = small_specs(3, 11)
+    ref = []
+    for s in specs:
+        d = build(capi, s, "fp16s")
+        d.step(s.steps)
+        ref.append(d.populations())
+        d.destroy()
+    failures = 0
+    for n in range(1, 9):
+        doms = [build(capi, s, "fp16s") for s in specs]
+        b = capi.Batch(1 << 33, "fp16s")
+        s0 = b.admit(doms[0], specs[0].steps)
+        b.step(2)
+        capi.check(capi.lbm_debug_fail_after(n))
+        failed = b.admit(doms[1], specs[1].steps)
+        capi.check(capi.lbm_debug_fail_after(0))
+        if failed is None:
+            failures += 1
+            # still stand-alone: a resident domain would refuse this call
+            assert doms[1].step_status(0) == capi.OK
+            s1 = b.admit(doms[1], specs[1].steps)
+        else:
+            s1 = failed
+        s2 = b.admit(doms[2], specs[2].steps)
+        slots = {s0: 0, s1: 1, s2: 2}
+        done = set()
+        while len(done) < 3:
+            b.step(4)
+            for s in b.poll():
+                assert s in slots, f"unknown slot {s} reported"
+                done.add(s)
+        for s, k in slots.items():
+            b.release(s)
+            assert np.array_equal(doms[k].populations(), ref[k]), f"injection {n}: domain {k} differs"
+            doms[k].destroy()
+        b.destroy()
+        say(f"failure injected at fallible step {n}: {'admission failed' if failed is None else 'no failure'}")
+    assert failures >= 4
+
+
+def test_serving_budget_bounds_device_memory(capi):
+    """Every byte the service holds on the device counts against its budget
+    (resident, released, prepared and waiting, being prepared): with room
+    for about two requests, the held bytes never exceed the budget; a
+    request that can never fit is answered with LBM_ERR_OOM and the others
+    are served; results equal the requests served alone."""
+    from paper_2204_10566_amd import serve
+
+    tr = I.serving_trace(count=6, rate=200.0, seed=9, steps_lo=20, steps_hi=60)
+    for r in tr:
+        n = 32 if r.rid % 2 else 40
+        r.nozzle = I.Nozzle(n=n, length=4 * n, R=n / 4.0, r_throat=n / 4.0 * 0.4, inlet_len=n / 2.0,
+                            throat_len=n)
+    big = max(serve.estimate_device_bytes(r, "fp16s") for r in tr)
+    budget = int(2.5 * big)
+    giant = tr[3]
+    giant.nozzle = I.Nozzle(n=96, length=384, R=24.0, r_throat=9.6, inlet_len=48.0, throat_len=96.0)
+    assert serve.estimate_device_bytes(giant, "fp16s") > budget
+    say(f"serving under a budget of {budget} bytes, one request too large")
+    mix, s_mix = serve.serve_continuous(tr, storage="fp16s", budget_bytes=budget, steps_per_tick=4,
+                                        keep_fields=True, realtime=False, work_cap_cells=None)
+    say(f"  peak held {s_mix['peak_held_bytes']} of {budget}")
+    assert 0 < s_mix["peak_held_bytes"] <= budget
+    alone, _ = serve.serve_serial([r for r in tr if r.rid != giant.rid], storage="fp16s", keep_fields=True,
+                                  realtime=False)
+    by = {o.rid: o for o in alone}
+    for o in mix:
+        if o.rid == giant.rid:
+            assert o.status == capi.ERR_OOM
+            continue
+        a = by[o.rid]
+        assert o.status == a.status == 0
         assert np.array_equal(o.rho, a.rho) and np.array_equal(o.u, a.u), f"request {o.rid} differs"
 
 
