@@ -34,7 +34,25 @@ enum : int { ST_FP32 = 0, ST_FP16S = 1, ST_BF16S = 2 };
 #ifndef LBM_STORE_AUX
 #define LBM_STORE_AUX 0
 #endif
+#ifndef LBM_SETPRIO
+#define LBM_SETPRIO 3
+#endif
 constexpr uint32_t kWavesPerBlock = LBM_WAVES_PER_BLOCK;
+
+// Wave priority while a wave issues its loads (LBM_SETPRIO > 0), back to 0
+// for the collision, so that waves starting a tile get their loads out
+// ahead of the collisions of the waves already resident (about 1 % on the
+// benchmark nozzle).
+__device__ __forceinline__ void prio_loads()
+{
+    if constexpr (LBM_SETPRIO > 0)
+        __builtin_amdgcn_s_setprio(LBM_SETPRIO);
+}
+__device__ __forceinline__ void prio_compute()
+{
+    if constexpr (LBM_SETPRIO > 0)
+        __builtin_amdgcn_s_setprio(0);
+}
 constexpr uint32_t kBlock = 64 * kWavesPerBlock;
 enum : uint8_t { FL_FLUID = 0, FL_SOLID = 1, FL_INLET = 2, FL_OUTLET = 3 };
 
@@ -232,6 +250,15 @@ template <> struct Storage<ST_BF16S> {
     }
 };
 
+// j / rho from inv = rcp(rho): the product j inv, corrected by one residual
+// step (q + (j - rho q) inv), which rounds to within an ulp with no
+// preferred sign.
+__device__ __forceinline__ float quotient(float j, float rho, float inv)
+{
+    const float q = j * inv;
+    return __builtin_fmaf(__builtin_fmaf(-rho, q, j), inv, q);
+}
+
 // ---------------------------------------------------------------------------
 // Collision: f <- T(u)^-1 M*, M = T(u) f (Sec. 2.1, Eqs. (6)-(8)).
 //
@@ -286,10 +313,15 @@ __device__ __forceinline__ float collide_h1(float (&f)[Q], float omega, float om
         sxz += s1[b + 6] - s1[b];
     }
     const float syz = (s0[8] + s0[0]) - (s0[6] + s0[2]);
+    // This form drops the first central moments (zero by definition of u),
+    // so the momentum it hands on is rho u: u must be j / rho to within a
+    // rounding of either sign.  j times a rounded 1 / rho errs to one side
+    // for densities near 1 (about 1e-8 relative per step, which a long run
+    // accumulates); one residual step per component removes that.
     const float inv = __builtin_amdgcn_rcpf(rho);
-    ux = jx * inv;
-    uy = jy * inv;
-    uz = jz * inv;
+    ux = quotient(jx, rho, inv);
+    uy = quotient(jy, rho, inv);
+    uz = quotient(jz, rho, inv);
     // central second-order Hermite moments, relaxed: off-diagonal and
     // deviator at omega, trace at omega_b (Sec. 2.1 after Eq. (8))
     const float ks = 1.f - omega, kb = 1.f - omega_b;
@@ -801,6 +833,7 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
     const bool wall = rec.wall >= 0;
     if (wall && !lane_active(rec, lane))
         return;
+    prio_loads();
 
     float f[Q];
     uint32_t m = 0;
@@ -834,6 +867,7 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
         }
     }
 
+    prio_compute();
     float ux, uy, uz, m2[6];
     const float rho = collide_lane<V, DYN>(d, f, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
@@ -956,6 +990,7 @@ __device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec
     const bool wall = rec.wall >= 0;
     if (wall && !lane_active(rec, lane))
         return;
+    prio_loads();
     const uint32_t self = rec.tile * d.tbytes + lane * es;
     // the outlet-plane cell: lane 63 of the last tile of its row
     const bool edge_lane = EDGE && lane == 63u && rec.tile - fdiv(rec.tile, d.drow) * d.rowtiles == d.rowtiles - 1u;
@@ -989,6 +1024,7 @@ __device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec
         }
     }
 
+    prio_compute();
     float ux, uy, uz, m2[6];
     const float rho = collide_lane<V, DYN>(d, f, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
@@ -1067,6 +1103,7 @@ __device__ __forceinline__ void local_load(const KDomain &d, const TileRec &rec,
     constexpr uint32_t es = S::bytes;
     const auto r = make_rsrc(d.buf, d.bufbytes);
     const uint32_t self = cell_bytes<es>(rec.tile * 64u + lane, d.tbytes);
+    prio_loads();
     if (rec.wall < 0 || lane_active(rec, lane)) {
 #pragma unroll
         for (int k = 0; k < Q; ++k)
@@ -1101,6 +1138,7 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
         if (rec.wall >= 0 && rec.bz)
             curved_walls(d, rec, lane, f);
     }
+    prio_compute();
     float ux, uy, uz, m2[6];
     const float rho = collide_lane<V, DYN>(d, f, ux, uy, uz, m2);
     check_state(d, rho, ux, uy, uz);
