@@ -194,6 +194,39 @@ def test_full_size_nozzle_sampled(capi, orc, which, storage):
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16s"])
+def test_full_size_nozzle_sampled_12_steps(capi, orc, storage):
+    """The benchmark nozzle (96x96x768, Re 500) 12 steps deep, replayed from
+    the step graphs of 8 and 4 steps as a timed run replays them, at 40
+    sampled cells (inlet-adjacent, outlet, wall-adjacent, random) against
+    the oracle's dependency-cone run.  Bounds four times those of 3 steps
+    (the per-step rounding adds up): FP32 4e-6, FP16S 8e-5 max abs.  The
+    200-step full-size comparison with FP64 is in test_gpu_precision."""
+    cfg = I.nozzle_config("re500")
+    fl, tau = cfg["flags"], cfg["tau"]
+    u0 = cfg["u0"].astype(np.float32)
+    uin = cfg["uin"].astype(np.float32)
+    steps = 12
+    say(f"nozzle re500 {fl.shape} {storage} {steps} steps")
+    d = run_gpu(capi, fl, 0, steps, tau=tau, u0=u0, uin=uin, storage=storage)
+    fg = d.populations().reshape(27, -1)
+    d.destroy()
+    upd = np.flatnonzero(updated(fl).ravel())
+    nx_ = fl.shape[2]
+    xs = upd % nx_
+    rng = np.random.default_rng(12)
+    solid = fl.ravel() == I.SOLID
+    near = upd[solid[np.clip(upd + nx_, 0, fl.size - 1)] | solid[np.clip(upd - nx_, 0, fl.size - 1)]]
+    picks = [rng.choice(upd[xs == 1], 10, replace=False), rng.choice(upd[xs == nx_ - 1], 10, replace=False),
+             rng.choice(upd, 10, replace=False), rng.choice(near, 10, replace=False)]
+    cells = np.unique(np.concatenate(picks))
+    st, fo = orc.run_cells(fl, cells, orc.rates_vector(1 / tau), steps, periodic=0, uin=uin, u0=u0)
+    assert st == 0
+    err = np.abs(fg[:, cells] - fo).max()
+    say(f"nozzle re500 {storage} {steps} steps: {cells.size} cells, max abs err {err:.3e}")
+    assert err <= (4e-6 if storage == "fp32" else 8e-5)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s"])
 def test_tgv320_probe_sampled(capi, orc, storage):
     """The benchmark's bandwidth probe: the periodic Taylor-Green vortex on
     320^3 cells (3.5 GB of FP32 populations, the largest array of the tests,
