@@ -118,8 +118,12 @@ typedef struct lbm_domain_info {
  *   hip_stream   hipStream_t to issue work on, or NULL for a stream the
  *                library creates.  The stream must outlive the domain.
  * Allocates the population array and initialises f = f^eq(1, 0).
- * A domain needs lbm_array_bytes(...) <= 4 GiB - 64 KiB (the kernels
- * address the array with 32-bit byte offsets).
+ * A domain has at most 2^32 - 64 cells (cell indices are 32-bit).  Arrays
+ * of up to 4 GiB - 64 KiB (lbm_array_bytes) are stepped by kernels that
+ * address them with buffer instructions and 32-bit byte offsets; larger
+ * ones by kernels with 64-bit global addresses (lbm_is_wide).  The device
+ * memory is the other bound: 288 GB hold about 2.6e9 FP32 or 5.2e9 FP16
+ * cells' populations.
  * Errors: LBM_ERR_ARG (bad sizes, flags or storage), LBM_ERR_OOM,
  * LBM_ERR_DEVICE.
  */
@@ -363,7 +367,9 @@ int lbm_batch_create(size_t hbm_budget_bytes, int storage, void *hip_stream, lbm
  * step.  The domain's state stays where it is (no copy).  The call does not
  * wait for work in flight.  Returns LBM_ERR_OOM when the domain does not fit
  * the remaining budget (the caller keeps it queued), LBM_ERR_STATE if the
- * domain is already resident.  *slot receives the slot id.
+ * domain is already resident, LBM_ERR_ARG if its population array exceeds
+ * 4 GiB - 64 KiB (the packed kernels address with 32-bit byte offsets).
+ * *slot receives the slot id.
  */
 int lbm_batch_admit(lbm_batch *b, lbm_domain *d, int n_steps, int *slot);
 
@@ -410,6 +416,19 @@ int lbm_selftest_host(void);
  * fails as if device memory were exhausted; n = 0 disables.  Returns
  * LBM_ERR_ARG for n < 0. */
 int lbm_debug_fail_after(int n);
+
+/* *wide = 1 if the domain's step kernels address its array with 64-bit
+ * global instructions (an array past 4 GiB - 64 KiB, or the test hook
+ * below), 0 if with 32-bit buffer offsets. */
+int lbm_is_wide(const lbm_domain *d, int *wide);
+
+/* Test hook: on = 1 makes a domain of any size step with the 64-bit
+ * addressing kernels of arrays past 4 GiB, so that they can be compared
+ * with the 32-bit ones on small grids (the two give the same bits); on = 0
+ * returns to the choice by size.  Packed steps always take the 32-bit
+ * kernels.  Errors: LBM_ERR_ARG for other values of on, LBM_ERR_STATE while
+ * the domain is resident in a batch. */
+int lbm_debug_wide_addressing(lbm_domain *d, int on);
 
 /* Library version string. */
 const char *lbm_version(void);

@@ -1,8 +1,9 @@
 """Build the gfx950 shared library liblbm.so in-tree with hipcc.
 
 The kernels of each storage format are compiled in their own translation
-unit (csrc/lbm_kern.hip with LBM_KERN_ST = 0, 1, 2), in parallel with the
-host translation unit (csrc/lbm.hip), and linked into one library.
+units (csrc/lbm_kern.hip with LBM_KERN_ST = 0, 1, 2; LBM_KERN_WIDE = 1 for
+the step kernels of arrays past 4 GiB), in parallel with the host
+translation unit (csrc/lbm.hip), and linked into one library.
 
 Usage: python -m paper_2204_10566_amd.build  (or build() from Python).
 """
@@ -38,6 +39,9 @@ UNITS = [
     ("lbm_kern.hip", ["-DLBM_KERN_ST=0"], "lbm_kern_fp32.o"),
     ("lbm_kern.hip", ["-DLBM_KERN_ST=1"], "lbm_kern_fp16s.o"),
     ("lbm_kern.hip", ["-DLBM_KERN_ST=2"], "lbm_kern_bf16s.o"),
+    ("lbm_kern.hip", ["-DLBM_KERN_ST=0", "-DLBM_KERN_WIDE=1"], "lbm_kern_fp32_wide.o"),
+    ("lbm_kern.hip", ["-DLBM_KERN_ST=1", "-DLBM_KERN_WIDE=1"], "lbm_kern_fp16s_wide.o"),
+    ("lbm_kern.hip", ["-DLBM_KERN_ST=2", "-DLBM_KERN_WIDE=1"], "lbm_kern_bf16s_wide.o"),
 ]
 
 

@@ -67,6 +67,8 @@ SIGNATURES = {
     "lbm_get_moments_noalloc": (ctypes.c_int, [_vp, _fp, _fp]),
     "lbm_set_equilibrium_order": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lbm_debug_fail_after": (ctypes.c_int, [ctypes.c_int]),
+    "lbm_debug_wide_addressing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lbm_is_wide": (ctypes.c_int, [_vp, _ip]),
     "lbm_get_populations": (ctypes.c_int, [_vp, _fp]),
     "lbm_set_populations": (ctypes.c_int, [_vp, _fp]),
     "lbm_domain_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(DomainInfo)]),
@@ -166,6 +168,18 @@ class Domain:
         """Order of the equilibrium the collision relaxes to: 6 (full, the
         paper's) or 2..5 (explicit truncated equilibrium)."""
         check(lbm_set_equilibrium_order(self.h, int(order)))
+
+    def is_wide(self):
+        """True if the step kernels address the array with 64-bit global
+        instructions (arrays past 4 GiB)."""
+        w = ctypes.c_int(0)
+        check(lbm_is_wide(self.h, ctypes.byref(w)))
+        return bool(w.value)
+
+    def debug_wide_addressing(self, on=True):
+        """Test hook: step with the 64-bit addressing kernels whatever the
+        size (on=False returns to the choice by size)."""
+        check(lbm_debug_wide_addressing(self.h, 1 if on else 0))
 
     def set_outlet(self, kind="zero_gradient", rho_out=1.0):
         """Outlet condition: "zero_gradient" or "pressure" (rho_out)."""

@@ -32,6 +32,9 @@ namespace lbm {
 LBM_INSTANCES(extern template, ST_FP32)
 LBM_INSTANCES(extern template, ST_FP16S)
 LBM_INSTANCES(extern template, ST_BF16S)
+LBM_INSTANCES_WIDE(extern template, ST_FP32)
+LBM_INSTANCES_WIDE(extern template, ST_FP16S)
+LBM_INSTANCES_WIDE(extern template, ST_BF16S)
 } // namespace lbm
 
 using namespace lbm;
@@ -231,6 +234,10 @@ void build_tiles(const uint8_t *flags, int nx, int ny, int nz, unsigned per, con
 constexpr int kGraphSizes = 6;
 constexpr int graph_len(int j) { return 64 >> j; }
 
+// Largest population array the buffer-instruction kernels address (their
+// byte offsets are 32-bit); larger arrays take the 64-bit kernels.
+constexpr uint64_t kNarrowBytes = (1ull << 32) - (1ull << 16);
+
 // Bytes of a domain's population array: the tile blocks, then 2 x 9 side
 // rows of ny * nz elements, rounded up to 256 bytes.
 uint64_t array_bytes(uint64_t P, int ny, int nz, int storage)
@@ -281,6 +288,10 @@ struct lbm_domain {
         return (explicit_feq() ? kVarFeq : (high1() ? kVarH1 : 0)) | (curved() ? kVarCurved : 0) |
                (outlet_kind == LBM_OUTLET_PRESSURE ? kVarPressure : 0);
     }
+    bool force_wide = false; // lbm_debug_wide_addressing
+    // the step kernels address the array with 64-bit global instructions
+    // (past the 4 GiB that buffer instructions reach)
+    bool wide() const { return force_wide || bytes > kNarrowBytes; }
     bool unstable = false;
     hipGraphExec_t graph[kGraphSizes] = {};   // graph j runs graph_len(j) steps from phase 0
     hipGraph_t graph_def[kGraphSizes] = {};
@@ -360,8 +371,8 @@ KDomain kdomain(const lbm_domain *d)
     k.status = d->d_status;
     k.P = (uint32_t)d->P;
     k.tbytes = (uint32_t)(Q * 64 * storage_bytes(d->storage));
-    k.side = (uint32_t)(d->P / 64 * k.tbytes);
-    k.bufbytes = (uint32_t)d->bytes;
+    k.side = d->P / 64 * k.tbytes;
+    k.bufbytes = d->bytes <= kNarrowBytes ? (uint32_t)d->bytes : 0u; // read by the narrow kernels only
     k.nx = d->nx;
     k.ny = d->ny;
     k.nz = d->nz;
@@ -490,24 +501,36 @@ template <class Fn> decltype(auto) with_kernel(int storage, int v, Fn &&fn)
     });
 }
 
+// The step kernel of a phase: the streaming step (phase 0) with row-aligned
+// or general addressing, or the local step; narrow or wide (Pops).
+const void *step_kernel(int storage, int v, uint32_t phase, bool rows, bool wide)
+{
+    return with_kernel(storage, v, [&](auto st, auto vc) -> const void * {
+        constexpr int ST = decltype(st)::value, V = decltype(vc)::value;
+        if (wide) {
+            if (phase == 1)
+                return (const void *)k_local_collide<ST, V, true>;
+            return rows ? (const void *)k_stream_collide<ST, V, true, true>
+                        : (const void *)k_stream_collide<ST, V, false, true>;
+        }
+        if (phase == 1)
+            return (const void *)k_local_collide<ST, V, false>;
+        return rows ? (const void *)k_stream_collide<ST, V, true, false>
+                    : (const void *)k_stream_collide<ST, V, false, false>;
+    });
+}
+
 hipError_t launch_step(const lbm_domain *d, uint32_t phase)
 {
     if (d->ntiles == 0)
         return hipSuccess;
-    const KDomain k = kdomain(d);
-    with_kernel(d->storage, d->variant(), [&](auto st, auto v) {
-        constexpr int ST = decltype(st)::value, V = decltype(v)::value;
-        if (phase == 0 && k.rowtiles)
-            hipLaunchKernelGGL((k_stream_collide<ST, V, true>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k,
-                               d->d_tiles, (uint32_t)d->ntiles);
-        else if (phase == 0)
-            hipLaunchKernelGGL((k_stream_collide<ST, V, false>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k,
-                               d->d_tiles, (uint32_t)d->ntiles);
-        else
-            hipLaunchKernelGGL((k_local_collide<ST, V>), dim3(step_grid(d)), dim3(kBlock), 0, d->stream, k,
-                               d->d_tiles, (uint32_t)d->ntiles);
-    });
-    return hipGetLastError();
+    KDomain k = kdomain(d);
+    const TileRec *tiles = d->d_tiles;
+    uint32_t nt = (uint32_t)d->ntiles;
+    void *args[] = {&k, &tiles, &nt};
+    const hipError_t e = hipLaunchKernel(step_kernel(d->storage, d->variant(), phase, k.rowtiles != 0, d->wide()),
+                                         dim3(step_grid(d)), dim3(kBlock), args, 0, d->stream);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 // Rebuild the inlet terms of the inlet tiles from the inlet velocity (all
@@ -637,11 +660,9 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     const uint64_t ncells = (uint64_t)nx * ny * nz;
     const uint64_t P = plane_stride(ncells);
     const uint64_t bufbytes = array_bytes(P, ny, nz, storage);
-    // buffer instructions take 32-bit byte offsets: every slot and side-row
-    // element must be addressable by one
-    if (bufbytes > (1ull << 32) - (1ull << 16))
-        return fail(LBM_ERR_ARG, "domain of %llu cells needs %llu bytes of populations; the limit is 4 GiB",
-                    (unsigned long long)ncells, (unsigned long long)bufbytes);
+    // cell indices are 32-bit
+    if (P > (1ull << 32) - 64)
+        return fail(LBM_ERR_ARG, "domain of %llu cells; the limit is 2^32 - 64 cells", (unsigned long long)ncells);
     std::vector<uint64_t> inlet_cells;
     bool outlets = false;
     for (uint64_t c = 0; c < ncells; ++c) {
@@ -747,15 +768,6 @@ hipError_t add_kernel_node(hipGraph_t g, hipGraphNode_t prev, const void *func, 
     return hipGraphAddKernelNode(out, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
 }
 
-const void *step_kernel(int storage, int v, uint32_t phase, bool rows)
-{
-    return with_kernel(storage, v, [&](auto st, auto vc) -> const void * {
-        constexpr int ST = decltype(st)::value, V = decltype(vc)::value;
-        if (phase == 1)
-            return (const void *)k_local_collide<ST, V>;
-        return rows ? (const void *)k_stream_collide<ST, V, true> : (const void *)k_stream_collide<ST, V, false>;
-    });
-}
 
 // Build (not capture) the step graphs: graph j chains graph_len(j) step
 // nodes starting in phase 0.  Built node by node so that work other threads
@@ -771,7 +783,7 @@ int build_graph(lbm_domain *d)
         HIP_TRY(hipGraphCreate(&g, 0));
         hipGraphNode_t prev = nullptr;
         for (int s = 0; s < graph_len(j); ++s) {
-            const void *fn = step_kernel(d->storage, d->variant(), (uint32_t)(s & 1), k.rowtiles != 0);
+            const void *fn = step_kernel(d->storage, d->variant(), (uint32_t)(s & 1), k.rowtiles != 0, d->wide());
             void *args[] = {&k, &tiles, &nt};
             hipGraphNode_t node = nullptr;
             hipError_t e = add_kernel_node(g, prev, fn, step_grid(d), kBlock, args, &node);
@@ -864,6 +876,29 @@ int lbm_set_equilibrium_order(lbm_domain *d, int order)
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     d->feq_order = order;
     d->graph_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_debug_wide_addressing(lbm_domain *d, int on)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (on != 0 && on != 1)
+        return fail(LBM_ERR_ARG, "on must be 0 or 1");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    d->force_wide = on == 1;
+    d->graph_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_is_wide(const lbm_domain *d, int *wide)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!wide)
+        return fail(LBM_ERR_ARG, "wide is null");
+    *wide = d->wide() ? 1 : 0;
     return LBM_OK;
 }
 

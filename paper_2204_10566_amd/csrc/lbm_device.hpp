@@ -110,10 +110,10 @@ struct KDomain {
     const uint32_t *wall;    // link masks of wall tiles, 64 per wall tile
     const float *iterm;      // inlet terms, [27][64] per inlet tile
     uint32_t *status;        // bit 0: a step went unstable
+    uint64_t side;           // byte offset of the side rows: 2 x 9 rows of ny * nz elements
     uint32_t P;              // cells rounded up to whole tiles
     uint32_t tbytes;         // bytes of one tile block: 27 x 64 populations
-    uint32_t side;           // byte offset of the side rows: 2 x 9 rows of ny * nz elements
-    uint32_t bufbytes;       // bytes of the whole array
+    uint32_t bufbytes;       // bytes of the whole array (below 4 GiB; see Pops)
     uint32_t nx, ny, nz, ncells;
     FastDiv dnx, dny;
     uint32_t periodic;
@@ -155,9 +155,12 @@ static_assert(sizeof(TileRec) == 40, "tile record layout");
 // byte tile * tbytes + (64 i + l) * es.  A wave writes one contiguous
 // block, and reads each neighbouring row's three populations that share
 // (cy, cz) as one contiguous run, which keeps HBM accesses long.
-template <uint32_t ES> __device__ __forceinline__ uint32_t cell_bytes(uint32_t cell, uint32_t tbytes)
+template <uint32_t ES, class Off = uint32_t> __device__ __forceinline__ Off cell_bytes(uint32_t cell, uint32_t tbytes)
 {
-    return __umul24(cell >> 6, tbytes) + (cell & 63u) * ES;
+    if constexpr (sizeof(Off) == 4)
+        return __umul24(cell >> 6, tbytes) + (cell & 63u) * ES;
+    else
+        return (uint64_t)(cell >> 6) * tbytes + (cell & 63u) * ES;
 }
 template <uint32_t ES> constexpr uint32_t pop_bytes(int i) { return (uint32_t)i * 64u * ES; }
 
@@ -190,6 +193,7 @@ template <> struct Storage<ST_FP32> {
         return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LBM_LOAD_AUX);
     }
     __device__ static float from_raw(uint32_t b, int) { return __uint_as_float(b); }
+    __device__ static uint32_t to_raw(float v, int) { return __float_as_uint(v); }
     __device__ static void store_raw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t b)
     {
         __builtin_amdgcn_raw_buffer_store_b32(b, r, voff, soff, LBM_STORE_AUX);
@@ -215,6 +219,7 @@ template <> struct Storage<ST_FP16S> {
         return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LOAD_AUX);
     }
     __device__ static float from_raw(uint32_t b, int i) { return to_f(__builtin_bit_cast(_Float16, (uint16_t)b), i); }
+    __device__ static uint32_t to_raw(float v, int i) { return __builtin_bit_cast(uint16_t, from_f(v, i)); }
     __device__ static void store_raw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t b)
     {
         __builtin_amdgcn_raw_buffer_store_b16((uint16_t)b, r, voff, soff, LBM_STORE_AUX);
@@ -237,6 +242,7 @@ template <> struct Storage<ST_BF16S> {
         return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, LBM_LOAD_AUX);
     }
     __device__ static float from_raw(uint32_t b, int i) { return to_f((uint16_t)b, i); }
+    __device__ static uint32_t to_raw(float v, int i) { return from_f(v, i); }
     __device__ static void store_raw(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t b)
     {
         __builtin_amdgcn_raw_buffer_store_b16((uint16_t)b, r, voff, soff, LBM_STORE_AUX);
@@ -248,6 +254,47 @@ template <> struct Storage<ST_BF16S> {
         b += 0x7fffu + ((b >> 16) & 1u);
         return (uint16_t)(b >> 16);
     }
+};
+
+// Access to a domain's population array at byte offset v + s, v per lane and
+// s wave-uniform.  Arrays below 4 GiB take raw buffer instructions (v the
+// lane offset, s the instruction's scalar offset).  Buffer addressing forms
+// its offset sum in 32 bits, structured or raw, so it cannot reach past
+// 4 GiB from the base: larger arrays (W64) take global instructions on
+// 64-bit addresses buf + s + v, whose uniform part stays in scalar
+// registers.  The kernels compile once for each.
+template <int ST, bool W64> struct Pops;
+template <int ST> struct Pops<ST, false> {
+    using S = Storage<ST>;
+    using Off = uint32_t;
+    __amdgpu_buffer_rsrc_t r;
+    __device__ explicit Pops(const KDomain &d) : r(make_rsrc(d.buf, d.bufbytes)) {}
+    __device__ float load(Off v, Off s, int i) const { return S::load(r, v, s, i); }
+    __device__ void store(Off v, Off s, float x, int i) const { S::store(r, v, s, x, i); }
+    __device__ uint32_t raw(Off v, Off s) const { return S::raw(r, v, s); }
+    __device__ void store_raw(Off v, Off s, uint32_t b) const { S::store_raw(r, v, s, b); }
+};
+template <int ST> struct Pops<ST, true> {
+    using S = Storage<ST>;
+    using Off = uint64_t;
+    char *b;
+    __device__ explicit Pops(const KDomain &d) : b(d.buf) {}
+    __device__ uint32_t raw(Off v, Off s) const
+    {
+        if constexpr (S::bytes == 4)
+            return *(const uint32_t *)(b + s + v);
+        else
+            return *(const uint16_t *)(b + s + v);
+    }
+    __device__ void store_raw(Off v, Off s, uint32_t x) const
+    {
+        if constexpr (S::bytes == 4)
+            *(uint32_t *)(b + s + v) = x;
+        else
+            *(uint16_t *)(b + s + v) = (uint16_t)x;
+    }
+    __device__ float load(Off v, Off s, int i) const { return S::from_raw(raw(v, s), i); }
+    __device__ void store(Off v, Off s, float x, int i) const { store_raw(v, s, S::to_raw(x, i)); }
 };
 
 // j / rho from inv = rcp(rho): the product j inv, corrected by one residual
@@ -708,10 +755,10 @@ __device__ __forceinline__ bool lane_active(const TileRec &rec, uint32_t lane)
 // Byte offset of side row element (h, j, plane cell (y, z)): h = 0 holds
 // f*_k of the last-plane cells for the nine c_x = -1 directions k = 3 j,
 // h = 1 the leaving f*_k of the outlet cells for k = 3 j + 2.
-template <uint32_t ES>
-__device__ __forceinline__ uint32_t side_bytes(const KDomain &d, uint32_t h, uint32_t j, uint32_t y, uint32_t z)
+template <uint32_t ES, class Off = uint32_t>
+__device__ __forceinline__ Off side_bytes(const KDomain &d, uint32_t h, uint32_t j, uint32_t y, uint32_t z)
 {
-    return d.side + ((h * 9u + j) * (d.ny * d.nz) + z * d.ny + y) * ES;
+    return (Off)d.side + ((Off)(h * 9u + j) * (d.ny * d.nz) + z * d.ny + y) * ES;
 }
 
 // Plane coordinate y + dy wrapped or checked against the box; false if it
@@ -810,25 +857,27 @@ __device__ __forceinline__ void curved_keep(const KDomain &d, const TileRec &rec
 // On that plane such a link is either the outlet's clamped link or a
 // bounce-back link (a fluid cell there has no source beyond the box), and a
 // bounce-back link uses the lane's own slot instead (selected by the mask).
-template <uint32_t ES>
-__device__ __forceinline__ uint32_t slot_of(const KDomain &d, const Coords &C, int k, bool edge_lane, uint32_t h)
+template <uint32_t ES, class Off = uint32_t>
+__device__ __forceinline__ Off slot_of(const KDomain &d, const Coords &C, int k, bool edge_lane, uint32_t h)
 {
     if (edge_lane && k % 3 == 0) {
         const int j = k / 3;
-        return h == 0u ? side_bytes<ES>(d, 0u, (uint32_t)j, C.sy[j % 3], C.sz[j / 3])
-                       : side_bytes<ES>(d, 1u, (uint32_t)(8 - j), C.y, C.z);
+        return h == 0u ? side_bytes<ES, Off>(d, 0u, (uint32_t)j, C.sy[j % 3], C.sz[j / 3])
+                       : side_bytes<ES, Off>(d, 1u, (uint32_t)(8 - j), C.y, C.z);
     }
-    return cell_bytes<ES>(C.row[k / 3] + C.sx[k % 3], d.tbytes) + pop_bytes<ES>(Q - 1 - k);
+    return cell_bytes<ES, Off>(C.row[k / 3] + C.sx[k % 3], d.tbytes) + pop_bytes<ES>(Q - 1 - k);
 }
 
 // Phase 0 -> 1.  EDGE: the tile has cells on the outlet plane (tile entry
 // `edge`); the other tiles compile without the outlet handling.
-template <int ST, int V, bool EDGE, bool DYN = false>
+template <int ST, int V, bool EDGE, bool DYN = false, bool W64 = false>
 __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     using S = Storage<ST>;
+    using P = Pops<ST, W64>;
+    using Off = typename P::Off;
     constexpr uint32_t es = S::bytes;
-    const auto r = make_rsrc(d.buf, d.bufbytes);
+    const P r(d);
     const uint32_t lin = rec.tile * 64u + lane;
     const bool wall = rec.wall >= 0;
     if (wall && !lane_active(rec, lane))
@@ -842,19 +891,19 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
         if (!wall) {
 #pragma unroll
             for (int k = 0; k < Q; ++k)
-                f[k] = S::load(r, cell_bytes<es>(C.row[k / 3] + C.sx[k % 3], d.tbytes), pop_bytes<es>(Q - 1 - k), k);
+                f[k] = r.load(cell_bytes<es, Off>(C.row[k / 3] + C.sx[k % 3], d.tbytes), pop_bytes<es>(Q - 1 - k), k);
         } else {
             // The per-cell mask picks each link's slot: the own slot of a
             // bounce-back link, else a_k.  (Loading both candidates before
             // the mask arrives and selecting afterwards measured slower: it
             // issues twice the load instructions.)
-            const uint32_t self = cell_bytes<es>(lin, d.tbytes);
+            const Off self = cell_bytes<es, Off>(lin, d.tbytes);
             const bool edge_lane = EDGE && C.x == d.nx - 1u;
             m = d.wall[(uint32_t)rec.wall * 64u + lane];
 #pragma unroll
             for (int k = 0; k < Q; ++k)
-                f[k] = S::load(r, ((m >> k) & 1u) ? self + pop_bytes<es>(k) : slot_of<es>(d, C, k, edge_lane, 0u),
-                               0u, k);
+                f[k] = r.load(((m >> k) & 1u) ? self + pop_bytes<es>(k) : slot_of<es, Off>(d, C, k, edge_lane, 0u),
+                              0u, k);
             if (rec.inlm) {
 #pragma unroll
                 for (int k = 0; k < Q; ++k)
@@ -899,7 +948,7 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
             if (plane_step(C.y, cy(k), d.ny, d.periodic & 2u, ty) && plane_step(C.z, cz(k), d.nz, d.periodic & 4u, tz)) {
                 const uint32_t t = (tz * d.ny + ty) * d.nx + d.nx - 1u;
                 if (d.flags[t] == FL_OUTLET)
-                    S::store(r, cell_bytes<es>(t, d.tbytes), pop_bytes<es>(k), pressure ? f[k] + g[j] : f[k], k);
+                    r.store(cell_bytes<es, Off>(t, d.tbytes), pop_bytes<es>(k), pressure ? f[k] + g[j] : f[k], k);
             }
         }
     }
@@ -917,16 +966,16 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
         for (int k = 0; k < Q; ++k) {
             uint32_t rowk = C.row[k / 3];
             asm volatile("" : "+v"(rowk)::"memory");
-            S::store(r, cell_bytes<es>(rowk + C.sx[k % 3], d.tbytes), pop_bytes<es>(Q - 1 - k), f[Q - 1 - k], k);
+            r.store(cell_bytes<es, Off>(rowk + C.sx[k % 3], d.tbytes), pop_bytes<es>(Q - 1 - k), f[Q - 1 - k], k);
         }
     } else {
-        const uint32_t self = cell_bytes<es>(lin2, d.tbytes);
+        const Off self = cell_bytes<es, Off>(lin2, d.tbytes);
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
             Coords Ck = C;
             asm volatile("" : "+v"(Ck.row[k / 3])::"memory");
-            S::store(r, ((m >> k) & 1u) ? self + pop_bytes<es>(k) : slot_of<es>(d, Ck, k, edge_lane, 1u), 0u,
-                     f[Q - 1 - k], k);
+            r.store(((m >> k) & 1u) ? self + pop_bytes<es>(k) : slot_of<es, Off>(d, Ck, k, edge_lane, 1u), 0u,
+                    f[Q - 1 - k], k);
         }
     }
 }
@@ -941,17 +990,17 @@ __device__ __forceinline__ void stream_tile_t(const KDomain &d, const TileRec &r
 // arithmetic of stream_tile_t.  On the outlet plane (EDGE) the only cell of
 // a tile is its lane 63, and the side-row elements it uses and the outlet
 // cells it feeds have wave-uniform addresses too.
-struct RowAddr {
+template <class Off> struct RowAddr {
     uint32_t y, z, j; // the tile's row and its position in the row
     uint32_t xo[3];   // by c_x + 1: byte offset of cell (x - c_x) from the start of its row
     uint32_t sy[3], sz[3];
-    uint32_t row[9];  // by (c_y + 1) + 3 (c_z + 1): byte offset of the first tile of the source row
+    Off row[9];       // by (c_y + 1) + 3 (c_z + 1): byte offset of the first tile of the source row
 };
 
-template <uint32_t ES>
-__device__ __forceinline__ RowAddr row_addr(const KDomain &d, const TileRec &rec, uint32_t lane)
+template <uint32_t ES, class Off = uint32_t>
+__device__ __forceinline__ RowAddr<Off> row_addr(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
-    RowAddr A;
+    RowAddr<Off> A;
     const uint32_t R = d.rowtiles, q = fdiv(rec.tile, d.drow);
     A.j = rec.tile - q * R;
     A.z = fdiv(q, d.dny);
@@ -975,42 +1024,45 @@ __device__ __forceinline__ RowAddr row_addr(const KDomain &d, const TileRec &rec
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-            A.row[b + 3 * c] = (A.sz[c] * d.ny + A.sy[b]) * R * d.tbytes;
+            A.row[b + 3 * c] = (Off)(A.sz[c] * d.ny + A.sy[b]) * (R * d.tbytes);
     return A;
 }
 
 // Phase 0 -> 1 for a tile of a row-aligned domain: stream_tile_t with the
 // addressing above.  EDGE: the tile holds a cell of the outlet plane.
-template <int ST, int V, bool EDGE, bool DYN = false>
+template <int ST, int V, bool EDGE, bool DYN = false, bool W64 = false>
 __device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     using S = Storage<ST>;
+    using P = Pops<ST, W64>;
+    using Off = typename P::Off;
     constexpr uint32_t es = S::bytes;
-    const auto r = make_rsrc(d.buf, d.bufbytes);
+    const P r(d);
     const bool wall = rec.wall >= 0;
     if (wall && !lane_active(rec, lane))
         return;
     prio_loads();
-    const uint32_t self = rec.tile * d.tbytes + lane * es;
+    const Off self = (Off)rec.tile * d.tbytes + lane * es;
     // the outlet-plane cell: lane 63 of the last tile of its row
     const bool edge_lane = EDGE && lane == 63u && rec.tile - fdiv(rec.tile, d.drow) * d.rowtiles == d.rowtiles - 1u;
 
     float f[Q];
     uint32_t m = 0;
     {
-        const RowAddr A = row_addr<es>(d, rec, lane);
+        const RowAddr<Off> A = row_addr<es, Off>(d, rec, lane);
         if (!wall) {
 #pragma unroll
             for (int k = 0; k < Q; ++k)
-                f[k] = S::load(r, A.xo[k % 3], A.row[k / 3] + pop_bytes<es>(Q - 1 - k), k);
+                f[k] = r.load(A.xo[k % 3], A.row[k / 3] + pop_bytes<es>(Q - 1 - k), k);
         } else {
             m = d.wall[(uint32_t)rec.wall * 64u + lane];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                uint32_t off = A.xo[k % 3] + A.row[k / 3] + pop_bytes<es>(Q - 1 - k);
+                Off off = A.xo[k % 3] + A.row[k / 3] + pop_bytes<es>(Q - 1 - k);
                 if (EDGE && k % 3 == 0) // the clamped upstream value of an outlet cell
-                    off = edge_lane ? side_bytes<es>(d, 0u, (uint32_t)k / 3u, A.sy[(k / 3) % 3], A.sz[k / 9]) : off;
-                f[k] = S::load(r, ((m >> k) & 1u) ? self + pop_bytes<es>(k) : off, 0u, k);
+                    off = edge_lane ? side_bytes<es, Off>(d, 0u, (uint32_t)k / 3u, A.sy[(k / 3) % 3], A.sz[k / 9])
+                                    : off;
+                f[k] = r.load(((m >> k) & 1u) ? self + pop_bytes<es>(k) : off, 0u, k);
             }
             if (rec.inlm) {
 #pragma unroll
@@ -1036,7 +1088,7 @@ __device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec
     // the lane index keeps the compiler from holding them through it)
     uint32_t lane2 = lane;
     asm volatile("" : "+v"(lane2) : "v"(f[0]), "v"(f[13]), "v"(f[26]));
-    const RowAddr A = row_addr<es>(d, rec, lane2);
+    const RowAddr<Off> A = row_addr<es, Off>(d, rec, lane2);
     if constexpr (EDGE) {
         // the outlet-plane cell hands the clamped values to the outlet cells
         // it feeds, cell (nx - 1, y + c_y, z + c_z) for direction k = 3 j
@@ -1053,7 +1105,7 @@ __device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec
             if (plane_step(A.y, cy(k), d.ny, d.periodic & 2u, ty) && plane_step(A.z, cz(k), d.nz, d.periodic & 4u, tz)) {
                 const uint32_t t = (tz * d.ny + ty) * d.nx + d.nx - 1u;
                 if (d.flags[t] == FL_OUTLET && edge_lane)
-                    S::store(r, cell_bytes<es>(t, d.tbytes), pop_bytes<es>(k), pressure ? f[k] + g[jj] : f[k], k);
+                    r.store(cell_bytes<es, Off>(t, d.tbytes), pop_bytes<es>(k), pressure ? f[k] + g[jj] : f[k], k);
             }
         }
     }
@@ -1063,16 +1115,16 @@ __device__ __forceinline__ void stream_tile_rows(const KDomain &d, const TileRec
         for (int k = 0; k < Q; ++k)
             f[Q - 1 - k] += inlet_term(d, rec, lane, k);
     }
-    const uint32_t self2 = rec.tile * d.tbytes + lane2 * es;
+    const Off self2 = (Off)rec.tile * d.tbytes + lane2 * es;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
         if (!wall) {
-            S::store(r, A.xo[k % 3], A.row[k / 3] + pop_bytes<es>(Q - 1 - k), f[Q - 1 - k], k);
+            r.store(A.xo[k % 3], A.row[k / 3] + pop_bytes<es>(Q - 1 - k), f[Q - 1 - k], k);
         } else {
-            uint32_t off = A.xo[k % 3] + A.row[k / 3] + pop_bytes<es>(Q - 1 - k);
+            Off off = A.xo[k % 3] + A.row[k / 3] + pop_bytes<es>(Q - 1 - k);
             if (EDGE && k % 3 == 0) // an outlet cell parks its leaving value
-                off = edge_lane ? side_bytes<es>(d, 1u, 8u - (uint32_t)k / 3u, A.y, A.z) : off;
-            S::store(r, ((m >> k) & 1u) ? self2 + pop_bytes<es>(k) : off, 0u, f[Q - 1 - k], k);
+                off = edge_lane ? side_bytes<es, Off>(d, 1u, 8u - (uint32_t)k / 3u, A.y, A.z) : off;
+            r.store(((m >> k) & 1u) ? self2 + pop_bytes<es>(k) : off, 0u, f[Q - 1 - k], k);
         }
     }
 }
@@ -1096,18 +1148,19 @@ __device__ __forceinline__ void stream_tile(const KDomain &d, const TileRec &rec
 // Phase 1 -> 0, in two halves so that a wave can issue the loads of its
 // next tile before it collides the current one.  Lanes of cells that are
 // not updated load nothing and store nothing.
-template <int ST>
+template <int ST, bool W64 = false>
 __device__ __forceinline__ void local_load(const KDomain &d, const TileRec &rec, uint32_t lane, float (&f)[Q])
 {
-    using S = Storage<ST>;
-    constexpr uint32_t es = S::bytes;
-    const auto r = make_rsrc(d.buf, d.bufbytes);
-    const uint32_t self = cell_bytes<es>(rec.tile * 64u + lane, d.tbytes);
+    using P = Pops<ST, W64>;
+    using Off = typename P::Off;
+    constexpr uint32_t es = Storage<ST>::bytes;
+    const P r(d);
+    const Off self = cell_bytes<es, Off>(rec.tile * 64u + lane, d.tbytes);
     prio_loads();
     if (rec.wall < 0 || lane_active(rec, lane)) {
 #pragma unroll
         for (int k = 0; k < Q; ++k)
-            f[k] = S::load(r, self, pop_bytes<es>(k), k);
+            f[k] = r.load(self, pop_bytes<es>(k), k);
     } else {
 #pragma unroll
         for (int k = 0; k < Q; ++k)
@@ -1124,16 +1177,17 @@ __device__ __forceinline__ void local_load(const KDomain &d, const TileRec &rec,
 // exactly in FP64 from the FP32 velocities, so that averages over long
 // windows keep their digits and the Reynolds stress <u_a u_b> - <u_a><u_b>
 // does not cancel away.
-template <int ST, int V, bool DYN = false>
+template <int ST, int V, bool DYN = false, bool W64 = false>
 __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &rec, uint32_t lane, float (&f)[Q])
 {
-    using S = Storage<ST>;
-    constexpr uint32_t es = S::bytes;
+    using P = Pops<ST, W64>;
+    using Off = typename P::Off;
+    constexpr uint32_t es = Storage<ST>::bytes;
     if (rec.wall >= 0 && !lane_active(rec, lane))
         return;
-    const auto r = make_rsrc(d.buf, d.bufbytes);
+    const P r(d);
     const uint32_t lin = rec.tile * 64u + lane;
-    const uint32_t self = cell_bytes<es>(lin, d.tbytes);
+    const Off self = cell_bytes<es, Off>(lin, d.tbytes);
     if constexpr ((V & kVarCurved) != 0) {
         if (rec.wall >= 0 && rec.bz)
             curved_walls(d, rec, lane, f);
@@ -1148,7 +1202,7 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-        S::store(r, self, pop_bytes<es>(Q - 1 - k), f[k], k);
+        r.store(self, pop_bytes<es>(Q - 1 - k), f[k], k);
     if (d.stats) {
         double *acc = d.stats + rec.ord * 64u + lane;
         const float ks = -(1.f - 0.5f * d.omega);
@@ -1170,18 +1224,18 @@ __device__ __forceinline__ void local_finish(const KDomain &d, const TileRec &re
                 outlet_ghost_shift(d, rho, ux, uy, uz, g);
 #pragma unroll
             for (int j = 0; j < 9; ++j)
-                S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, pressure ? f[3 * j] + g[j] : f[3 * j],
-                         3 * j);
+                r.store(side_bytes<es, Off>(d, 0u, (uint32_t)j, y, z), 0u, pressure ? f[3 * j] + g[j] : f[3 * j],
+                        3 * j);
         }
     }
 }
 
-template <int ST, int V, bool DYN = false>
+template <int ST, int V, bool DYN = false, bool W64 = false>
 __device__ __forceinline__ void local_tile(const KDomain &d, const TileRec &rec, uint32_t lane)
 {
     float f[Q];
-    local_load<ST>(d, rec, lane, f);
-    local_finish<ST, V, DYN>(d, rec, lane, f);
+    local_load<ST, W64>(d, rec, lane, f);
+    local_finish<ST, V, DYN, W64>(d, rec, lane, f);
 }
 
 #ifdef LBM_HOST_TU
@@ -1236,8 +1290,9 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) { return (
 // grid covers every tile).
 // Streaming step of a single domain; ROWS: the domain is row-aligned
 // (stream_tile_rows), chosen per domain on the host, so that each kernel
-// carries only one addressing scheme.
-template <int ST, int V, bool ROWS>
+// carries only one addressing scheme; W64: the array reaches past 4 GiB
+// (Pops).
+template <int ST, int V, bool ROWS, bool W64>
 __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const TileRec *__restrict__ tiles,
                                                            uint32_t ntiles)
 {
@@ -1249,19 +1304,19 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(KDomain d, const Tile
         const TileRec rec = tiles[t];
         if constexpr (ROWS) {
             if (rec.edge)
-                stream_tile_rows<ST, V, true>(d, rec, lane);
+                stream_tile_rows<ST, V, true, false, W64>(d, rec, lane);
             else
-                stream_tile_rows<ST, V, false>(d, rec, lane);
+                stream_tile_rows<ST, V, false, false, W64>(d, rec, lane);
         } else {
             if (rec.edge)
-                stream_tile_t<ST, V, true>(d, rec, lane);
+                stream_tile_t<ST, V, true, false, W64>(d, rec, lane);
             else
-                stream_tile_t<ST, V, false>(d, rec, lane);
+                stream_tile_t<ST, V, false, false, W64>(d, rec, lane);
         }
     }
 }
 
-template <int ST, int V>
+template <int ST, int V, bool W64>
 __global__ __launch_bounds__(kBlock) void k_local_collide(KDomain d, const TileRec *__restrict__ tiles,
                                                           uint32_t ntiles)
 {
@@ -1270,7 +1325,7 @@ __global__ __launch_bounds__(kBlock) void k_local_collide(KDomain d, const TileR
     const uint32_t w0 =
         __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));
     for (uint32_t t = w0; t < ntiles; t += nw)
-        local_tile<ST, V>(d, tiles[t], lane);
+        local_tile<ST, V, false, W64>(d, tiles[t], lane);
 }
 
 // Packed multi-domain step, one kernel per phase.  ctrl[0] / ctrl[2] =
@@ -1341,26 +1396,27 @@ __global__ __launch_bounds__(256) void k_normalise(KDomain d, const TileRec *__r
     const TileRec rec = tiles[t];
     if (rec.wall >= 0 && !lane_active(rec, lane))
         return;
-    const auto r = make_rsrc(d.buf, d.bufbytes);
+    const Pops<ST, true> r(d);
     const uint32_t lin = rec.tile * 64u + lane;
     const Coords C = coords(d, lin);
-    const uint32_t self = cell_bytes<es>(lin, d.tbytes);
+    const uint64_t self = cell_bytes<es, uint64_t>(lin, d.tbytes);
     const uint32_t m = rec.wall >= 0 ? d.wall[(uint32_t)rec.wall * 64u + lane] : 0u;
     const bool edge_lane = rec.edge && C.x == d.nx - 1u;
     for (int k = 0; k < Q; ++k) {
         if ((m >> k) & 1u) {
             if ((rec.inlm >> k) & 1u) {
-                const float v = S::load(r, self, pop_bytes<es>(k), k) - inlet_term(d, rec, lane, k);
-                S::store(r, self, pop_bytes<es>(k), v, k);
+                const float v = r.load(self, pop_bytes<es>(k), k) - inlet_term(d, rec, lane, k);
+                r.store(self, pop_bytes<es>(k), v, k);
             }
         } else if (edge_lane && k % 3 == 0) {
-            S::store_raw(r, slot_of<es>(d, C, k, true, 0u), 0u, S::raw(r, self + pop_bytes<es>(k), 0u));
-            S::store_raw(r, self + pop_bytes<es>(k), 0u, S::raw(r, slot_of<es>(d, C, k, true, 1u), 0u));
+            r.store_raw(slot_of<es, uint64_t>(d, C, k, true, 0u), 0u, r.raw(self + pop_bytes<es>(k), 0u));
+            r.store_raw(self + pop_bytes<es>(k), 0u, r.raw(slot_of<es, uint64_t>(d, C, k, true, 1u), 0u));
         } else if (k > Q / 2) {
-            const uint32_t ak = cell_bytes<es>(C.row[k / 3] + C.sx[k % 3], d.tbytes) + pop_bytes<es>(Q - 1 - k);
-            const uint32_t u = S::raw(r, self + pop_bytes<es>(k), 0u), v = S::raw(r, ak, 0u);
-            S::store_raw(r, self + pop_bytes<es>(k), 0u, v);
-            S::store_raw(r, ak, 0u, u);
+            const uint64_t ak =
+                cell_bytes<es, uint64_t>(C.row[k / 3] + C.sx[k % 3], d.tbytes) + pop_bytes<es>(Q - 1 - k);
+            const uint32_t u = r.raw(self + pop_bytes<es>(k), 0u), v = r.raw(ak, 0u);
+            r.store_raw(self + pop_bytes<es>(k), 0u, v);
+            r.store_raw(ak, 0u, u);
         }
     }
 }
@@ -1381,18 +1437,18 @@ __global__ __launch_bounds__(256) void k_side_refresh(KDomain d)
     const uint32_t c = (z * d.ny + y) * d.nx + d.nx - 1u;
     if (d.flags[c] != FL_FLUID && d.flags[c] != FL_OUTLET)
         return;
-    const auto r = make_rsrc(d.buf, d.bufbytes);
-    const uint32_t cb = cell_bytes<es>(c, d.tbytes);
+    const Pops<ST, true> r(d);
+    const uint64_t cb = cell_bytes<es, uint64_t>(c, d.tbytes);
     if (!d.outlet) {
         for (int j = 0; j < 9; ++j)
-            S::store_raw(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u,
-                         S::raw(r, cb + pop_bytes<es>(Q - 1 - 3 * j), 0u));
+            r.store_raw(side_bytes<es, uint64_t>(d, 0u, (uint32_t)j, y, z), 0u,
+                        r.raw(cb + pop_bytes<es>(Q - 1 - 3 * j), 0u));
         return;
     }
     float f[Q], rho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        f[i] = S::load(r, cb, pop_bytes<es>(Q - 1 - i), i);
+        f[i] = r.load(cb, pop_bytes<es>(Q - 1 - i), i);
         rho += f[i];
         jx += (float)cx(i) * f[i];
         jy += (float)cy(i) * f[i];
@@ -1402,7 +1458,7 @@ __global__ __launch_bounds__(256) void k_side_refresh(KDomain d)
     outlet_ghost_shift(d, rho, jx / rho, jy / rho, jz / rho, g);
 #pragma unroll
     for (int j = 0; j < 9; ++j)
-        S::store(r, side_bytes<es>(d, 0u, (uint32_t)j, y, z), 0u, f[3 * j] + g[j], 3 * j);
+        r.store(side_bytes<es, uint64_t>(d, 0u, (uint32_t)j, y, z), 0u, f[3 * j] + g[j], 3 * j);
 }
 
 // bzaux from a phase-0 state (after an initialisation, an import or new
@@ -1420,12 +1476,12 @@ __global__ __launch_bounds__(256) void k_curved_refresh(KDomain d, const TileRec
     const TileRec rec = tiles[t];
     if (rec.wall < 0 || !rec.bz || !lane_active(rec, lane))
         return;
-    const auto r = make_rsrc(d.buf, d.bufbytes);
-    const uint32_t self = cell_bytes<es>(rec.tile * 64u + lane, d.tbytes);
+    const Pops<ST, true> r(d);
+    const uint64_t self = cell_bytes<es, uint64_t>(rec.tile * 64u + lane, d.tbytes);
     float f[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k)
-        f[k] = ((rec.bz >> k) & 1u) ? S::load(r, self, pop_bytes<es>(Q - 1 - k), k) : 0.f;
+        f[k] = ((rec.bz >> k) & 1u) ? r.load(self, pop_bytes<es>(Q - 1 - k), k) : 0.f;
     curved_keep(d, rec, lane, f);
 }
 
@@ -1450,8 +1506,8 @@ __global__ __launch_bounds__(256) void k_init_eq(KDomain d, const float *__restr
                 r = rho[c];
             if (u) {
                 v[0] = u[c];
-                v[1] = u[d.ncells + c];
-                v[2] = u[2u * d.ncells + c];
+                v[1] = u[(size_t)d.ncells + c];
+                v[2] = u[2 * (size_t)d.ncells + c];
             }
         }
     }
@@ -1463,12 +1519,12 @@ __global__ __launch_bounds__(256) void k_init_eq(KDomain d, const float *__restr
         phi[a][1] = 2.0f / 3.0f - w2;
         phi[a][2] = (1.f + 3.f * w + 3.f * w2) * (1.0f / 6.0f);
     }
-    const auto rr = make_rsrc(d.buf, d.bufbytes);
-    const uint32_t cb = cell_bytes<es>(c, d.tbytes);
+    const Pops<ST, true> rr(d);
+    const uint64_t cb = cell_bytes<es, uint64_t>(c, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float fe = upd ? r * phi[0][i % 3] * phi[1][(i / 3) % 3] * phi[2][i / 9] : weight(i);
-        S::store(rr, cb, pop_bytes<es>(Q - 1 - i), fe, i);
+        rr.store(cb, pop_bytes<es>(Q - 1 - i), fe, i);
     }
 }
 
@@ -1482,11 +1538,11 @@ __global__ __launch_bounds__(256) void k_moments(KDomain d, float *__restrict__ 
         return;
     float r = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
     if (d.flags[c] == FL_FLUID || d.flags[c] == FL_OUTLET) {
-        const auto rr = make_rsrc(d.buf, d.bufbytes);
-        const uint32_t cb = cell_bytes<S::bytes>(c, d.tbytes);
+        const Pops<ST, true> rr(d);
+        const uint64_t cb = cell_bytes<S::bytes, uint64_t>(c, d.tbytes);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float fi = S::load(rr, cb, pop_bytes<S::bytes>(Q - 1 - i), i);
+            const float fi = rr.load(cb, pop_bytes<S::bytes>(Q - 1 - i), i);
             r += fi;
             jx += (float)cx(i) * fi;
             jy += (float)cy(i) * fi;
@@ -1499,8 +1555,8 @@ __global__ __launch_bounds__(256) void k_moments(KDomain d, float *__restrict__ 
     }
     rho[c] = r;
     u[c] = jx;
-    u[d.ncells + c] = jy;
-    u[2u * d.ncells + c] = jz;
+    u[(size_t)d.ncells + c] = jy;
+    u[2 * (size_t)d.ncells + c] = jz;
 }
 
 #ifdef LBM_HOST_TU
@@ -1534,11 +1590,11 @@ __global__ __launch_bounds__(256) void k_export(KDomain d, float *__restrict__ o
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.ncells)
         return;
-    const auto rr = make_rsrc(d.buf, d.bufbytes);
-    const uint32_t cb = cell_bytes<S::bytes>(c, d.tbytes);
+    const Pops<ST, true> rr(d);
+    const uint64_t cb = cell_bytes<S::bytes, uint64_t>(c, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        out[(size_t)i * d.ncells + c] = S::load(rr, cb, pop_bytes<S::bytes>(Q - 1 - i), i);
+        out[(size_t)i * d.ncells + c] = rr.load(cb, pop_bytes<S::bytes>(Q - 1 - i), i);
 }
 
 template <int ST>
@@ -1548,11 +1604,11 @@ __global__ __launch_bounds__(256) void k_import(KDomain d, const float *__restri
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= d.ncells)
         return;
-    const auto rr = make_rsrc(d.buf, d.bufbytes);
-    const uint32_t cb = cell_bytes<S::bytes>(c, d.tbytes);
+    const Pops<ST, true> rr(d);
+    const uint64_t cb = cell_bytes<S::bytes, uint64_t>(c, d.tbytes);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        S::store(rr, cb, pop_bytes<S::bytes>(Q - 1 - i), in[(size_t)i * d.ncells + c], i);
+        rr.store(cb, pop_bytes<S::bytes>(Q - 1 - i), in[(size_t)i * d.ncells + c], i);
 }
 
 } // namespace lbm

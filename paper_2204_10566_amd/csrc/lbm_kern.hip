@@ -1,6 +1,7 @@
 // lbm_kern.hip -- compiles the kernels of one storage format
 // (LBM_KERN_ST = 0 FP32, 1 FP16S, 2 BF16S) into their own object, so that
-// the three formats build in parallel; lbm.hip launches them.
+// the formats build in parallel; lbm.hip launches them.  LBM_KERN_WIDE = 1
+// compiles the step kernels of arrays past 4 GiB instead.
 #include "lbm_device.hpp"
 #include "lbm_instances.hpp"
 
@@ -9,5 +10,9 @@
 #endif
 
 namespace lbm {
+#if LBM_KERN_WIDE
+LBM_INSTANCES_WIDE(template, LBM_KERN_ST)
+#else
 LBM_INSTANCES(template, LBM_KERN_ST)
+#endif
 } // namespace lbm

@@ -77,13 +77,16 @@ def test_create_rejects_bad_sizes(capi):
     assert capi.lbm_create_domain(None, 2, 2, 2, 0, 0, None, ctypes.byref(h)) == capi.ERR_ARG
 
 
-def test_too_large_domain_rejected(capi):
-    # 27 * P * 4 bytes must stay below 4 GiB for FP32
-    n = 40 * 1024 * 1024
-    fl = np.zeros(n, np.uint8)
+def test_too_many_cells_rejected(capi):
+    """Cell indices are 32-bit: a grid of more than 2^32 - 64 cells is
+    refused from its sizes, before the flags are read (so a one-byte flag
+    buffer suffices here).  Arrays past 4 GiB are accepted; they step with
+    the 64-bit addressing kernels (tests/test_gpu_wide.py)."""
+    fl = np.zeros(1, np.uint8)
     h = ctypes.c_void_p()
-    rc = capi.lbm_create_domain(fl.ctypes.data_as(capi._u8p), 1024, 1024, 40, 0, 0, None, ctypes.byref(h))
-    assert rc == capi.ERR_ARG and "4 GiB" in capi.lbm_last_error().decode()
+    rc = capi.lbm_create_domain(fl.ctypes.data_as(capi._u8p), 65535, 65535, 2, 0, 0, None, ctypes.byref(h))
+    assert rc == capi.ERR_ARG and "2^32 - 64 cells" in capi.lbm_last_error().decode()
+    assert not h.value
 
 
 def test_null_handles(capi):

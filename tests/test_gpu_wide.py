@@ -1,0 +1,148 @@
+"""Population arrays past 4 GiB.
+
+Buffer instructions form their byte offsets in 32 bits, so arrays larger
+than 4 GiB - 64 KiB step with kernels that take 64-bit global addresses.
+Those kernels run the same arithmetic in the same order: on the random
+configurations of every boundary option (test_gpu_random_configs) and on
+each storage, equilibrium order and statistics, forcing them onto a small
+domain gives the same bits as the 32-bit kernels.  Then a genuine 4.8 GB
+FP32 domain, periodic in z, whose flags and initial fields repeat a small
+block K times along z: by translation invariance every block of it must
+end bit for bit equal to the small block stepped alone, which exercises
+slots, side rows and the periodic wrap across the whole array."""
+import numpy as np
+import pytest
+
+from paper_2204_10566_amd import inputs as I
+
+from test_gpu_random_configs import build_domain, make_case
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def capi():
+    from paper_2204_10566_amd import capi
+
+    return capi
+
+
+def run_case(capi, c, storage, wide, steps, feq=6, stats=False):
+    d = build_domain(capi, c, storage)
+    if feq != 6:
+        d.set_equilibrium_order(feq)
+    if wide:
+        d.debug_wide_addressing(True)
+    assert d.is_wide() == wide
+    if stats:
+        d.stats_enable(True)
+    d.step(steps)
+    out = [d.populations(), *d.moments()]
+    if stats:
+        out += list(d.stats()[:3])
+    d.destroy()
+    return out
+
+
+@pytest.mark.parametrize("k", range(24))
+def test_wide_kernels_give_the_same_bits(capi, k):
+    c = make_case(300 + k)
+    storage = ("fp32", "fp16s", "bf16s")[k % 3]
+    feq = (6, 6, 3, 6, 2, 6)[k % 6]
+    steps = 2 * c["steps"] + 1  # odd: ends in the local phase
+    stats = k % 4 == 1
+    say(f"case {k}: shape {c['fl'].shape} periodic {c['periodic']} {storage} order {feq} steps {steps} "
+        f"outlet {c['outlet']} curved {c['q'] is not None} stats {stats}")
+    narrow = run_case(capi, c, storage, False, steps, feq, stats)
+    wide = run_case(capi, c, storage, True, steps, feq, stats)
+    for a, b in zip(narrow, wide):
+        assert np.array_equal(a, b)
+
+
+def test_graphs_and_phase_switch(capi):
+    """Switching to the wide kernels mid-run, with graph replays on both
+    sides of the switch, continues the same trajectory."""
+    c = make_case(11, "fp32")
+    ref = run_case(capi, c, "fp32", False, 75)[0]
+    d = build_domain(capi, c, "fp32")
+    d.step(33)
+    d.debug_wide_addressing(True)
+    d.step(40)
+    d.debug_wide_addressing(False)
+    d.step(2)
+    f = d.populations()
+    d.destroy()
+    assert np.array_equal(f, ref)
+
+
+def block_fields(shape, seed):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    rho = (1.0 + 0.02 * rng.uniform(-1, 1, shape)).astype(np.float32)
+    u = (0.04 * rng.uniform(-1, 1, (3,) + shape)).astype(np.float32)
+    return rho, u
+
+
+def tiled_case(general):
+    """A block repeated along a periodic z axis: y walls, an inlet plane, an
+    outlet plane and a few solid cells per block; nx = 128 (row-aligned
+    addressing) or 100 (general addressing)."""
+    if general:
+        nx, ny, nz0, K = 100, 40, 5, 2200
+    else:
+        nx, ny, nz0, K = 128, 48, 6, 1200
+    fl = np.zeros((nz0, ny, nx), np.uint8)
+    fl[:, 0, :] = I.SOLID
+    fl[:, -1, :] = I.SOLID
+    fl[:, 1:-1, 0] = I.INLET
+    fl[:, 1:-1, -1] = I.OUTLET
+    fl[1:3, 10:14, 30:33] = I.SOLID
+    uin = np.zeros((3,) + fl.shape, np.float32)
+    uin[0][fl == I.INLET] = 0.05
+    return fl, uin, K
+
+
+@pytest.mark.parametrize("general,outlet", [(False, None), (True, ("pressure", 0.995))])
+def test_domain_past_4_gib(capi, general, outlet):
+    fl0, uin0, K = tiled_case(general)
+    nz0, ny, nx = fl0.shape
+    rho0, u0 = block_fields(fl0.shape, 7)
+    steps = 7
+    say(f"block {fl0.shape} x {K} along z, outlet {outlet}: small run")
+    small = capi.Domain(fl0, periodic=4, storage="fp32")
+    small.set_params(0.56)
+    if outlet:
+        small.set_outlet(*outlet)
+    small.set_inlet(uin0)
+    small.init_fields(rho0, u0)
+    small.step(steps)
+    fs = small.populations()
+    small.destroy()
+
+    fl = np.tile(fl0, (K, 1, 1))
+    nbytes = capi.lbm_array_bytes(nx, ny, nz0 * K, 0)
+    say(f"  big domain {fl.shape}: {fl.size} cells, {nbytes / 1e9:.2f} GB of populations")
+    assert nbytes > 1 << 32
+    big = capi.Domain(fl, periodic=4, storage="fp32")
+    assert big.is_wide()
+    big.set_params(0.56)
+    if outlet:
+        big.set_outlet(*outlet)
+    big.set_inlet(np.tile(uin0, (1, K, 1, 1)))
+    big.init_fields(np.tile(rho0, (K, 1, 1)), np.tile(u0, (1, K, 1, 1)))
+    b = capi.Batch(1 << 36, "fp32")
+    with pytest.raises(capi.LbmError) as e:
+        b.admit(big, 1)
+    assert e.value.code == capi.ERR_ARG
+    b.destroy()
+    big.step(steps)
+    say("  stepped; comparing every block")
+    fb = big.populations().reshape(27, K, nz0, ny, nx)
+    big.destroy()
+    bad = [j for j in range(K) if not np.array_equal(fb[:, j], fs)]
+    say(f"  blocks differing from the small run: {len(bad)} of {K}")
+    assert not bad

@@ -51,7 +51,7 @@ def test_library_host_code_under_sanitizers(tmp_path):
              "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
              "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_device", "-O0", "-Xarch_device", "-g0",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-    units = [("lbm.hip", [], "host.o")] + [("lbm_kern.hip", [f"-DLBM_KERN_ST={st}"], f"k{st}.o") for st in range(3)]
+    from paper_2204_10566_amd.build import UNITS as units  # every translation unit of the library
     procs = [subprocess.Popen(["hipcc", *flags, *extra, "-c", os.path.join(CSRC, src), "-o", str(tmp_path / obj)],
                               stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
              for src, extra, obj in units]
