@@ -291,6 +291,54 @@ def roofline_probe_leg(capi, torch, stream, n=320, steps=192):
     return out
 
 
+def finest_grid_leg(capi, torch, stream, steps=64):
+    """The synthetic nozzle on the paper's finest grid (Table 2, R4: cells of
+    0.0776 mm over the 12 x 12 x 240 mm domain, 155 x 155 x 3093 = 74.3 M
+    cells) at Re 6500.  In FP32 its population array (8.0 GB) is past the
+    4 GiB that buffer instructions address, so it steps with the 64-bit
+    addressing kernels; in FP16S (4.0 GB) with the 32-bit ones.  nx = 3093 is
+    not a multiple of 64: general addressing.  From the plug-flow start, 64
+    untimed and `steps` timed steps."""
+    import numpy as np
+
+    from paper_2204_10566_amd import inputs as I
+
+    n, length = 155, 3093
+    nz = I.Nozzle(n=n, length=length, R=n / 4.0, r_throat=n / 12.0)
+    tau, u_thr = I.nozzle_tau(nz, 6500.0)
+    fl = nz.flags()
+    uin = nz.inlet_velocity_cells(u_thr, fl).astype(np.float32)
+    u0 = nz.initial_velocity(u_thr).astype(np.float32)
+    out = {"workload": f"synthetic nozzle {n}x{n}x{length} (x axial; the paper's R4 grid), Re 6500, tau = {tau:.6f}, "
+                       f"{steps} timed steps", "cells": int(fl.size)}
+    for st in ("fp32", "fp16s"):
+        d = capi.Domain(fl, periodic=0, storage=st, stream=stream.cuda_stream)
+        d.set_params(tau, 1.0 / tau, 1.0)
+        d.set_inlet_cells(uin)
+        d.init_fields(None, u0)
+        info = d.info()
+        wide = d.is_wide()
+        d.step(64)
+        d.prepare_steps()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        rc = d.step_status(steps)
+        e1.record(stream)
+        e1.synchronize()
+        d.destroy()
+        us = e0.elapsed_time(e1) / steps * 1e3
+        gbs = info.n_updated * info.bytes_per_cell_update / (us * 1e-6) / 1e9
+        out[st] = {"array_gb": round(capi.lbm_array_bytes(length, n, n, 0 if st == "fp32" else 1) / 1e9, 2),
+                   "addressing": "64-bit" if wide else "32-bit", "fluid_cells": int(info.n_updated),
+                   "us_per_step": round(us, 1), "mlups": round(info.n_updated / us, 1), "achieved_gbs": round(gbs, 1),
+                   "frac_of_peak": round(gbs / PEAK_HBM_GBS, 4), "status": int(rc)}
+        log(f"R4 nozzle {st}: {out[st]}")
+    out["ratio_fp16s_vs_fp32"] = round(out["fp16s"]["mlups"] / out["fp32"]["mlups"], 3)
+    return out
+
+
 def stability_leg(capi, stream):
     """Stability envelope at tau -> 1/2: a 64^3 periodic double shear layer
     (u0 = 0.1, FP32) run 2000 steps at decreasing tau - 1/2 for several
@@ -400,6 +448,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-stability", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--no-finest", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path: "
@@ -499,6 +548,9 @@ def main():
     if not args.no_probe:
         log("roofline probe: periodic TGV 320^3")
         out["roofline_probe"] = roofline_probe_leg(capi, torch, stream)
+    if not args.no_finest:
+        log("finest grid: the nozzle at 155x155x3093")
+        out["finest_grid"] = finest_grid_leg(capi, torch, stream)
     if not args.no_stability:
         log("stability envelope (double shear layer)")
         out["stability"] = stability_leg(capi, stream)
