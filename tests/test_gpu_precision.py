@@ -15,7 +15,11 @@ storage to 2^-11 of (f - w) 2^14, i.e. about 3e-5 absolute on f, BF16 to
 2^-8 of (f - w).  Over the first 200 steps the difference is that rounding,
 accumulated step by step (measured: FP32 5.5e-5, FP16 5.3e-4, BF16 4.9e-3):
 FP32 is held to 1e-4, FP16 to the 1e-3 velocity error the method is held
-to, BF16 to 1e-2.  Between steps 200 and 2000 the jet behind the throat is
+to, BF16 to 1e-2.  The pressure error is held to ten times the velocity
+bound: a storage rounding moves rho and j by sums of the same roundings,
+but e_p divides by the density fluctuation |rho - mean|, about 3 U^2 = 1e-2
+of rho at these speeds, against U = 6e-2 for e_u, a factor of about 6
+(measured e_p / e_u: 1.3 to 7.4).  Between steps 200 and 2000 the jet behind the throat is
 unstable at this Reynolds number: two FP64 oracle runs from starts 1e-7
 apart drift 200-fold further apart (a CPU test pins this on the stored
 fields), and the rounding of every step is amplified alike (measured: FP32
@@ -38,6 +42,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 BOUND_U = {"fp32": 1e-4, "fp16s": 1e-3, "bf16s": 1e-2}
+BOUND_P = {k: 10.0 * v for k, v in BOUND_U.items()}
 FULL_REF = os.path.join(GOLDEN, "precision_re6500_full_200_sampled.npz")
 
 
@@ -93,6 +98,7 @@ def test_precision_against_fp64_200_steps(capi, storage):
     say(f"re6500 quarter, 200 steps, {storage}: e_u={e_u:.3e} e_p={e_p:.3e}")
     assert st == 0
     assert e_u <= BOUND_U[storage]
+    assert e_p <= BOUND_P[storage]
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16s", "bf16s"])
@@ -109,6 +115,7 @@ def test_full_size_precision_against_fp64(capi, storage):
     say(f"re6500 128x128x1536, 200 steps, {storage}: e_u={e_u:.3e} e_p={e_p:.3e} at {cells.size} cells")
     assert st == 0
     assert e_u <= BOUND_U[storage]
+    assert e_p <= BOUND_P[storage]
 
 
 def test_fp32_2000_steps_within_flow_amplification(capi):
