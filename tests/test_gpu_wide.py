@@ -9,7 +9,9 @@ domain gives the same bits as the 32-bit kernels.  Then a genuine 4.8 GB
 FP32 domain, periodic in z, whose flags and initial fields repeat a small
 block K times along z: by translation invariance every block of it must
 end bit for bit equal to the small block stepped alone, which exercises
-slots, side rows and the periodic wrap across the whole array."""
+slots, side rows and the periodic wrap across the whole array.  Last, the
+nozzle on the paper's finest grid (8.0 GB in FP32) against the oracle at
+sampled cells."""
 import numpy as np
 import pytest
 
@@ -146,3 +148,46 @@ def test_domain_past_4_gib(capi, general, outlet):
     bad = [j for j in range(K) if not np.array_equal(fb[:, j], fs)]
     say(f"  blocks differing from the small run: {len(bad)} of {K}")
     assert not bad
+
+
+def test_finest_grid_sampled(capi, orc):
+    """The synthetic nozzle on the paper's finest grid (Table 2, R4: 155 x
+    155 x 3093 = 74.3 M cells, Re 6500): an 8.0 GB FP32 array, stepped by the
+    64-bit kernels with general addressing (nx = 3093).  After 3 steps from
+    the plug-flow start, density and velocity at sampled cells (next to the
+    inlet, on the outlet plane, next to a wall, anywhere, and at cells whose
+    slots lie past 4 GiB into the array) against the oracle's
+    dependency-cone run.  Bound: 27 populations of 3 steps at the per-step
+    FP32 bound 4e-7 each, 3.3e-5."""
+    n, length = 155, 3093
+    nz = I.Nozzle(n=n, length=length, R=n / 4.0, r_throat=n / 12.0)
+    tau, u_thr = I.nozzle_tau(nz, 6500.0)
+    fl = nz.flags()
+    uin = nz.inlet_velocity(u_thr).astype(np.float32)
+    u0 = nz.initial_velocity(u_thr).astype(np.float32)
+    say(f"finest grid {fl.shape}: {fl.size} cells, 3 steps")
+    d = capi.Domain(fl, periodic=0, storage="fp32")
+    assert d.is_wide()
+    d.set_params(tau, 1.0 / tau, 1.0)
+    d.set_inlet(uin)
+    d.init_fields(None, u0)
+    d.step(3)
+    rg, ug = d.moments()
+    d.destroy()
+    upd = np.flatnonzero(((fl == I.FLUID) | (fl == I.OUTLET)).ravel())
+    x = upd % length
+    solid = fl.ravel() == I.SOLID
+    near = upd[solid[np.clip(upd + length, 0, fl.size - 1)] | solid[np.clip(upd - length, 0, fl.size - 1)]]
+    rng = np.random.default_rng(74)
+    cells = np.unique(np.concatenate([rng.choice(upd[x == 1], 8, replace=False),
+                                      rng.choice(upd[x == length - 1], 8, replace=False),
+                                      rng.choice(near, 8, replace=False), rng.choice(upd, 8, replace=False),
+                                      rng.choice(upd[upd * 27 * 4 > 1 << 32], 8, replace=False)]))
+    st, fo = orc.run_cells(fl, cells, orc.rates_vector(1.0 / tau), 3, periodic=0, uin=uin, u0=u0)
+    assert st == 0
+    err = 0.0
+    for k, c in enumerate(cells):
+        ro, uo = orc.cell_moments(fo[:, k])
+        err = max(err, abs(float(rg.ravel()[c]) - ro), float(np.abs(ug.reshape(3, -1)[:, c] - uo).max()))
+    say(f"  {cells.size} cells: max abs err of rho and u {err:.3e}")
+    assert err <= 27 * 3 * 4e-7
