@@ -12,6 +12,7 @@ Tolerances (FP32 storage and arithmetic against FP64):
     to 11 significant bits, at most 2^-11 |f - w|, and these states keep
     |f - w| near 0.01).
 """
+import os
 import sys
 
 import numpy as np
@@ -224,6 +225,42 @@ def test_full_size_nozzle_sampled_12_steps(capi, orc, storage):
     err = np.abs(fg[:, cells] - fo).max()
     say(f"nozzle re500 {storage} {steps} steps: {cells.size} cells, max abs err {err:.3e}")
     assert err <= (4e-6 if storage == "fp32" else 8e-5)
+
+
+NOZZLE_REF = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "nozzle_re500_200_sampled.npz")
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s", "bf16s"])
+def test_bench_nozzle_200_steps_against_oracle(capi, storage):
+    """The benchmark nozzle (96x96x768, Re 500) over its first 200 steps
+    from the plug-flow start, stepped as the benchmark steps it (graph
+    replays), against the oracle's full FP64 run of the same window
+    (tests/golden/make_nozzle_reference.py): the 27 populations at 2048
+    sampled cells (next to the inlet, on the outlet plane, next to a wall,
+    in the throat and the expansion, anywhere) and the velocity at 16384.
+    The population bound is the per-step bound of the random configurations
+    times the steps (FP32 4e-7, FP16S 5e-5, BF16S 2e-4 per step); the
+    velocity error e_u (relative L2) is held to the bounds of the precision
+    comparison (FP32 1e-4, FP16S 1e-3, BF16S 1e-2)."""
+    ref = np.load(NOZZLE_REF)
+    steps = int(ref["steps"])
+    cfg = I.nozzle_config("re500")
+    fl, tau = cfg["flags"], cfg["tau"]
+    assert abs(tau - float(ref["tau"])) < 1e-15
+    say(f"nozzle re500 {fl.shape} {storage} {steps} steps against the FP64 oracle")
+    d = run_gpu(capi, fl, 0, steps, tau=tau, u0=cfg["u0"].astype(np.float32), uin=cfg["uin"].astype(np.float32),
+                storage=storage)
+    fg = d.populations().reshape(27, -1)
+    _, ug = d.moments()
+    d.destroy()
+    err = float(np.abs(fg[:, ref["pop_cells"]] - ref["f"]).max())
+    uo = ref["u"]
+    e_u = float(np.linalg.norm(ug.reshape(3, -1)[:, ref["moment_cells"]] - uo) / np.linalg.norm(uo))
+    per_step = {"fp32": 4e-7, "fp16s": 5e-5, "bf16s": 2e-4}[storage]
+    say(f"  populations at {ref['pop_cells'].size} cells: max abs err {err:.3e} (bound {per_step * steps:.1e}); "
+        f"e_u {e_u:.3e} at {ref['moment_cells'].size} cells")
+    assert err <= per_step * steps
+    assert e_u <= {"fp32": 1e-4, "fp16s": 1e-3, "bf16s": 1e-2}[storage]
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16s"])
