@@ -45,6 +45,29 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
+def read_kernel_profile(storage: str, workload: str):
+    """Per-kernel average durations of the step kernels from the committed
+    rocprofv3 kernel-trace summary, with the fraction of 8 TB/s each
+    reaches on the algorithmic bytes; None when absent or when the kernel
+    source has changed since the trace was taken."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", f"step_{storage}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"sha256\[:16\]: (\w+)", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    out = {"source": os.path.relpath(path, ROOT)}
+    for k in ("k_stream_collide", "k_local_collide"):
+        m = re.search(rf"  {k}: avg ([\d.]+) us -> (\d+) GB/s \(([\d.]+)% of 8 TB/s\)", text)
+        if m:
+            out[k] = {"avg_us": float(m.group(1)), "achieved_gbs": float(m.group(2)),
+                      "frac": round(float(m.group(3)) / 100, 4)}
+    return out
+
+
 def read_traffic(kernel: str, storage: str, workload: str):
     """HBM traffic per launch measured with rocprofv3 counters, from the
     committed summary; None when absent or when the kernel source has
@@ -522,6 +545,7 @@ def main():
             "bytes_per_fluid_cell": bpc,
             "copy_ceiling_gbs": copy["gbs"],
             "frac_of_copy": round(achieved / copy["gbs"], 4),
+            "per_kernel_rocprof": read_kernel_profile(args.storage, "nozzle96x96x768"),
         },
     }
     if not args.no_variants and args.storage == "fp32":
