@@ -430,6 +430,15 @@ int lbm_is_wide(const lbm_domain *d, int *wide);
  * the domain is resident in a batch. */
 int lbm_debug_wide_addressing(lbm_domain *d, int on);
 
+/* Test hook: blocks > 0 launches each step of the domain on that many
+ * blocks of 256 lanes (a multiple of 8, one block per XCD in turn), each
+ * wave walking the tile list with the grid's stride, instead of one wave
+ * per tile; blocks = 0 returns to the default.  Results do not depend on the
+ * launch shape (no two lanes of a step touch one slot), which the tests
+ * check bit for bit.  Errors: LBM_ERR_ARG for other values, LBM_ERR_STATE
+ * while the domain is resident in a batch. */
+int lbm_debug_step_grid(lbm_domain *d, int blocks);
+
 /* Library version string. */
 const char *lbm_version(void);
 

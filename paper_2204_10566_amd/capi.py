@@ -68,6 +68,7 @@ SIGNATURES = {
     "lbm_set_equilibrium_order": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lbm_debug_fail_after": (ctypes.c_int, [ctypes.c_int]),
     "lbm_debug_wide_addressing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lbm_debug_step_grid": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lbm_is_wide": (ctypes.c_int, [_vp, _ip]),
     "lbm_get_populations": (ctypes.c_int, [_vp, _fp]),
     "lbm_set_populations": (ctypes.c_int, [_vp, _fp]),
@@ -180,6 +181,11 @@ class Domain:
         """Test hook: step with the 64-bit addressing kernels whatever the
         size (on=False returns to the choice by size)."""
         check(lbm_debug_wide_addressing(self.h, 1 if on else 0))
+
+    def debug_step_grid(self, blocks=0):
+        """Test hook: launch each step on `blocks` blocks (a multiple of 8;
+        0 returns to one wave per tile)."""
+        check(lbm_debug_step_grid(self.h, int(blocks)))
 
     def set_outlet(self, kind="zero_gradient", rho_out=1.0):
         """Outlet condition: "zero_gradient" or "pressure" (rho_out)."""

@@ -289,6 +289,7 @@ struct lbm_domain {
                (outlet_kind == LBM_OUTLET_PRESSURE ? kVarPressure : 0);
     }
     bool force_wide = false; // lbm_debug_wide_addressing
+    uint32_t grid_blocks = 0; // lbm_debug_step_grid: blocks of a step launch (0: one wave per tile)
     // the step kernels address the array with 64-bit global instructions
     // (past the 4 GiB that buffer instructions reach)
     bool wide() const { return force_wide || bytes > kNarrowBytes; }
@@ -398,6 +399,8 @@ uint32_t grid8(uint64_t blocks) { return (uint32_t)((blocks + 7) / 8 * 8); }
 // measured slower).
 uint32_t step_grid(const lbm_domain *d)
 {
+    if (d->grid_blocks)
+        return d->grid_blocks;
     return grid8((d->ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
@@ -888,6 +891,19 @@ int lbm_debug_wide_addressing(lbm_domain *d, int on)
     if (d->batch)
         return fail(LBM_ERR_STATE, "domain is resident in a batch");
     d->force_wide = on == 1;
+    d->graph_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_debug_step_grid(lbm_domain *d, int blocks)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (blocks < 0 || blocks % 8 != 0 || blocks > (1 << 20))
+        return fail(LBM_ERR_ARG, "blocks must be 0 or a positive multiple of 8 up to 2^20, got %d", blocks);
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    d->grid_blocks = (uint32_t)blocks;
     d->graph_dirty = true;
     return LBM_OK;
 }
