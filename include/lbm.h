@@ -122,8 +122,8 @@ typedef struct lbm_domain_info {
  * of up to 4 GiB - 64 KiB (lbm_array_bytes) are stepped by kernels that
  * address them with buffer instructions and 32-bit byte offsets; larger
  * ones by kernels with 64-bit global addresses (lbm_is_wide).  The device
- * memory is the other bound: 288 GB hold about 2.6e9 FP32 or 5.2e9 FP16
- * cells' populations.
+ * memory is the other bound: 288 GB hold about 2.6e9 FP32 cells'
+ * populations (in FP16 the cell limit binds first).
  * Errors: LBM_ERR_ARG (bad sizes, flags or storage), LBM_ERR_OOM,
  * LBM_ERR_DEVICE.
  */
