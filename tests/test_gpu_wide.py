@@ -5,8 +5,9 @@ than 4 GiB - 64 KiB step with kernels that take 64-bit global addresses.
 Those kernels run the same arithmetic in the same order: on the random
 configurations of every boundary option (test_gpu_random_configs) and on
 each storage, equilibrium order and statistics, forcing them onto a small
-domain gives the same bits as the 32-bit kernels.  Then a genuine 4.8 GB
-FP32 domain, periodic in z, whose flags and initial fields repeat a small
+domain gives the same bits as the 32-bit kernels.  Then genuine 4.8 GB
+domains (FP32, and FP16S with twice the cells), periodic in z, whose flags
+and initial fields repeat a small
 block K times along z: by translation invariance every block of it must
 end bit for bit equal to the small block stepped alone, which exercises
 slots, side rows and the periodic wrap across the whole array.  Last, the
@@ -89,14 +90,17 @@ def block_fields(shape, seed):
     return rho, u
 
 
-def tiled_case(general):
+def tiled_case(general, storage="fp32"):
     """A block repeated along a periodic z axis: y walls, an inlet plane, an
     outlet plane and a few solid cells per block; nx = 128 (row-aligned
-    addressing) or 100 (general addressing)."""
+    addressing) or 100 (general addressing); in FP16 twice as many blocks
+    (the array holds half the bytes per cell)."""
     if general:
         nx, ny, nz0, K = 100, 40, 5, 2200
     else:
         nx, ny, nz0, K = 128, 48, 6, 1200
+    if storage != "fp32":
+        K *= 2
     fl = np.zeros((nz0, ny, nx), np.uint8)
     fl[:, 0, :] = I.SOLID
     fl[:, -1, :] = I.SOLID
@@ -108,14 +112,15 @@ def tiled_case(general):
     return fl, uin, K
 
 
-@pytest.mark.parametrize("general,outlet", [(False, None), (True, ("pressure", 0.995))])
-def test_domain_past_4_gib(capi, general, outlet):
-    fl0, uin0, K = tiled_case(general)
+@pytest.mark.parametrize("general,outlet,storage", [(False, None, "fp32"), (True, ("pressure", 0.995), "fp32"),
+                                                    (False, ("pressure", 1.002), "fp16s")])
+def test_domain_past_4_gib(capi, general, outlet, storage):
+    fl0, uin0, K = tiled_case(general, storage)
     nz0, ny, nx = fl0.shape
     rho0, u0 = block_fields(fl0.shape, 7)
     steps = 7
-    say(f"block {fl0.shape} x {K} along z, outlet {outlet}: small run")
-    small = capi.Domain(fl0, periodic=4, storage="fp32")
+    say(f"block {fl0.shape} x {K} along z, outlet {outlet}, {storage}: small run")
+    small = capi.Domain(fl0, periodic=4, storage=storage)
     small.set_params(0.56)
     if outlet:
         small.set_outlet(*outlet)
@@ -126,17 +131,17 @@ def test_domain_past_4_gib(capi, general, outlet):
     small.destroy()
 
     fl = np.tile(fl0, (K, 1, 1))
-    nbytes = capi.lbm_array_bytes(nx, ny, nz0 * K, 0)
+    nbytes = capi.lbm_array_bytes(nx, ny, nz0 * K, 0 if storage == "fp32" else 1)
     say(f"  big domain {fl.shape}: {fl.size} cells, {nbytes / 1e9:.2f} GB of populations")
     assert nbytes > 1 << 32
-    big = capi.Domain(fl, periodic=4, storage="fp32")
+    big = capi.Domain(fl, periodic=4, storage=storage)
     assert big.is_wide()
     big.set_params(0.56)
     if outlet:
         big.set_outlet(*outlet)
     big.set_inlet(np.tile(uin0, (1, K, 1, 1)))
     big.init_fields(np.tile(rho0, (K, 1, 1)), np.tile(u0, (1, K, 1, 1)))
-    b = capi.Batch(1 << 36, "fp32")
+    b = capi.Batch(1 << 36, storage)
     with pytest.raises(capi.LbmError) as e:
         b.admit(big, 1)
     assert e.value.code == capi.ERR_ARG
