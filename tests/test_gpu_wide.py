@@ -7,10 +7,10 @@ configurations of every boundary option (test_gpu_random_configs) and on
 each storage, equilibrium order and statistics, forcing them onto a small
 domain gives the same bits as the 32-bit kernels.  Then genuine 4.8 GB
 domains (FP32, and FP16S with twice the cells), periodic in z, whose flags
-and initial fields repeat a small
-block K times along z: by translation invariance every block of it must
-end bit for bit equal to the small block stepped alone, which exercises
-slots, side rows and the periodic wrap across the whole array.  Last, the
+and initial fields repeat a small block K times along z: by translation
+invariance every block of it must end bit for bit equal to the small block
+stepped alone, which exercises slots, side rows and the periodic wrap
+across the whole array.  Last, the
 nozzle on the paper's finest grid (8.0 GB in FP32) against the oracle at
 sampled cells."""
 import numpy as np
