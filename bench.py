@@ -315,29 +315,34 @@ def roofline_probe_leg(capi, torch, stream, n=320, steps=192):
 
 
 def finest_grid_leg(capi, torch, stream, steps=64):
-    """The synthetic nozzle on the paper's finest grid (Table 2, R4: cells of
-    0.0776 mm over the 12 x 12 x 240 mm domain, 155 x 155 x 3093 = 74.3 M
-    cells) at Re 6500.  In FP32 its population array (8.0 GB) is past the
-    4 GiB that buffer instructions address, so it steps with the 64-bit
-    addressing kernels; in FP16S (4.0 GB) with the 32-bit ones.  nx = 3093 is
-    not a multiple of 64: general addressing.  From the plug-flow start, 64
-    untimed and `steps` timed steps."""
+    """The synthetic nozzle on the paper's finest grid in that run's own
+    lattice parameters (Table 2, R4 at Re 6500: cells of 0.0776 mm over the
+    12 x 12 x 240 mm domain, 155 x 155 x 3093 = 74.3 M cells, the pipe filling
+    the cross-section; tau = 0.50281 and a mean throat velocity of 0.118 cells
+    per step, CFL 0.236), constant-pressure outlet, halfway walls.  In FP32 its
+    population array (8.0 GB) is past the 4 GiB that buffer instructions
+    address, so it steps with the 64-bit addressing kernels; in FP16S (4.0 GB)
+    with the 32-bit ones.  nx = 3093 is not a multiple of 64: general
+    addressing.  From the plug-flow start, 64 untimed and `steps` timed
+    steps."""
     import numpy as np
 
     from paper_2204_10566_amd import inputs as I
 
-    n, length = 155, 3093
-    nz = I.Nozzle(n=n, length=length, R=n / 4.0, r_throat=n / 12.0)
-    tau, u_thr = I.nozzle_tau(nz, 6500.0)
-    fl = nz.flags()
-    uin = nz.inlet_velocity_cells(u_thr, fl).astype(np.float32)
-    u0 = nz.initial_velocity(u_thr).astype(np.float32)
-    out = {"workload": f"synthetic nozzle {n}x{n}x{length} (x axial; the paper's R4 grid), Re 6500, tau = {tau:.6f}, "
-                       f"{steps} timed steps", "cells": int(fl.size)}
+    cfg = I.paper_nozzle("R4", 6500)
+    fl = cfg["flags"]
+    nz_, ny_, nx_ = fl.shape
+    uin = cfg["uin_cells"].astype(np.float32)
+    u0 = cfg["u0"].astype(np.float32)
+    tau = cfg["tau"]
+    out = {"workload": f"synthetic nozzle {ny_}x{nz_}x{nx_} (x axial) in the paper's R4 parameters (Table 2, Re 6500): "
+                       f"tau = {tau:.6f}, mean throat velocity {cfg['u_thr']:.4f}, pressure outlet, {steps} timed steps",
+           "cells": int(fl.size)}
     for st in ("fp32", "fp16s"):
         d = capi.Domain(fl, periodic=0, storage=st, stream=stream.cuda_stream)
         d.set_params(tau, 1.0 / tau, 1.0)
         d.set_inlet_cells(uin)
+        d.set_outlet("pressure", 1.0)
         d.init_fields(None, u0)
         info = d.info()
         wide = d.is_wide()
@@ -353,12 +358,53 @@ def finest_grid_leg(capi, torch, stream, steps=64):
         d.destroy()
         us = e0.elapsed_time(e1) / steps * 1e3
         gbs = info.n_updated * info.bytes_per_cell_update / (us * 1e-6) / 1e9
-        out[st] = {"array_gb": round(capi.lbm_array_bytes(length, n, n, 0 if st == "fp32" else 1) / 1e9, 2),
+        out[st] = {"array_gb": round(capi.lbm_array_bytes(nx_, ny_, nz_, 0 if st == "fp32" else 1) / 1e9, 2),
                    "addressing": "64-bit" if wide else "32-bit", "fluid_cells": int(info.n_updated),
                    "us_per_step": round(us, 1), "mlups": round(info.n_updated / us, 1), "achieved_gbs": round(gbs, 1),
                    "frac_of_peak": round(gbs / PEAK_HBM_GBS, 4), "status": int(rc)}
         log(f"R4 nozzle {st}: {out[st]}")
     out["ratio_fp16s_vs_fp32"] = round(out["fp16s"]["mlups"] / out["fp32"]["mlups"], 3)
+    return out
+
+
+def paper_regime_leg(capi, steps=20000):
+    """The paper's own parameter sets on its coarsest grid (Table 2, R1:
+    52 x 52 x 1043): Re 500 (tau = 0.50922, CFL 0.177) and Re 6500 (tau =
+    0.50100, CFL 0.249, a peak lattice velocity near 0.25), the synthetic
+    nozzle with a constant-pressure outlet, FP32, from the plug-flow start,
+    with halfway walls and with the curved walls the paper uses.  Reports
+    how many steps each runs before the status word reports an unstable
+    cell (all `steps` when it does not)."""
+    import numpy as np
+
+    from paper_2204_10566_amd import inputs as I
+
+    out = {"workload": f"synthetic nozzle on the R1 grid in the paper's parameters, up to {steps} steps, FP32"}
+    for re in (500, 6500):
+        cfg = I.paper_nozzle("R1", re)
+        fl = cfg["flags"]
+        q = cfg["nozzle"].wall_distances(fl)
+        for walls in ("halfway", "curved"):
+            d = capi.Domain(fl, periodic=0, storage="fp32")
+            d.set_params(cfg["tau"], 1.0 / cfg["tau"], 1.0)
+            if walls == "curved":
+                d.set_wall_distances(q)
+            d.set_inlet_cells(cfg["uin_cells"].astype(np.float32))
+            d.set_outlet("pressure", 1.0)
+            d.init_fields(None, cfg["u0"].astype(np.float32))
+            done, rc = 0, 0
+            while done < steps:
+                rc = d.step_status(1000)
+                if rc != 0:
+                    break
+                done += 1000
+            _, u = d.moments()
+            d.destroy()
+            key = f"re{re}_{walls}_walls"
+            out[key] = {"tau": round(cfg["tau"], 6), "mean_throat_velocity": round(cfg["u_thr"], 4),
+                        "stable_steps": done, "status": int(rc),
+                        "max_abs_u": None if rc else round(float(np.abs(u).max()), 4)}
+            log(f"paper regime R1 Re {re}, {walls} walls: {out[key]}")
     return out
 
 
@@ -472,6 +518,7 @@ def main():
     ap.add_argument("--no-stability", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-finest", action="store_true")
+    ap.add_argument("--no-regime", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path: "
@@ -575,6 +622,9 @@ def main():
     if not args.no_finest:
         log("finest grid: the nozzle at 155x155x3093")
         out["finest_grid"] = finest_grid_leg(capi, torch, stream)
+    if not args.no_regime:
+        log("the paper's own parameters on the R1 grid")
+        out["paper_regime"] = paper_regime_leg(capi)
     if not args.no_stability:
         log("stability envelope (double shear layer)")
         out["stability"] = stability_leg(capi, stream)

@@ -314,6 +314,25 @@ def nozzle_config(which: str = "re500") -> dict:
     }
 
 
+def paper_nozzle(name: str, re: int) -> dict:
+    """The synthetic nozzle on one of the paper's resolutions in that run's
+    own lattice parameters (Table 2 through paper_2204_10566_amd.units): the
+    pipe fills the 12 mm cross-section (radius n/2 - 1/2 cells), the throat
+    is a third of it, tau = 3 nu dt / dr^2 + 1/2 and the mean throat velocity
+    is half the CFL number of the run (in cells per step)."""
+    from . import units
+
+    r = units.resolution(name, re)
+    nz_, ny_, nx_ = r.cells
+    R = ny_ / 2.0 - 0.5
+    noz = Nozzle(n=ny_, length=nx_, R=R, r_throat=R / 3.0)
+    fl = noz.flags()
+    u_thr = r.lattice_throat_velocity
+    return {"nozzle": noz, "flags": fl, "uin_cells": noz.inlet_velocity_cells(u_thr, fl),
+            "u0": noz.initial_velocity(u_thr), "tau": r.tau, "u_thr": u_thr, "Re": float(re), "resolution": r,
+            "periodic": 0}
+
+
 def small_nozzle(n: int = 24, length: int = 160, R: float = 8.0, r_throat: float = 3.0, Re: float = 100.0):
     """A scaled-down nozzle for tests the oracle can run in full."""
     nz = Nozzle(n=n, length=length, R=R, r_throat=r_throat, inlet_len=2 * R, throat_len=3 * R)
