@@ -312,6 +312,52 @@ int lbm_get_populations(lbm_domain *d, float *f);
 int lbm_set_populations(lbm_domain *d, const float *f);
 
 /*
+ * Checkpoint and restart of a run.  The study's runs cover 300 flow-through
+ * periods and average over the second half (Sec. 2.2), far more steps than
+ * one job may hold a device for, so a run must be able to stop and resume.  lbm_get_populations / lbm_set_populations
+ * carry the populations f_i, from which the library rebuilds what else a
+ * step reads: the outlet cells' clamped values (with the pressure outlet's
+ * shift, from the moments of the stored post-collision state) and the
+ * curved walls' kept values; a run resumed that way agrees with the
+ * uninterrupted one to rounding.  The state calls below instead copy the
+ * domain's state exactly as the device holds it, so that a resumed run is
+ * bit for bit the uninterrupted one, in every storage:
+ *   - the population array as stored (lbm_array_bytes: the tiles in the
+ *     domain's storage format, then the outlet side rows), in whichever
+ *     phase the last step left it;
+ *   - the curved walls' kept values f*_k (27 * 64 floats per wall tile);
+ *   - the phase and the instability flag.
+ * Not in the state: the configuration (rates, equilibrium order, inlet
+ * velocities, outlet kind and density, wall fractions), which the caller
+ * sets on the restarted domain as on the original one, before or after
+ * lbm_load_state, and the statistics sums.
+ *
+ * The byte image: a 64-byte header of eight little-endian uint64 words
+ * (0: the tag "LBMSTAT1"; 1: nx | ny << 16 | nz << 32 | periodic << 48 |
+ * storage << 56; 2: array bytes; 3: kept curved-wall bytes; 4: FNV-1a 64
+ * of the flags the domain was created with; 5: phase | unstable << 1;
+ * 6, 7: zero), then the array, then the kept values.
+ */
+
+/* Bytes of the domain's state image (header, array, kept curved-wall
+ * values; the last part is 0 until wall fractions are set). */
+int lbm_state_bytes(const lbm_domain *d, size_t *bytes);
+
+/* Copy the state image into host memory buf of `bytes` bytes (at least
+ * lbm_state_bytes).  The domain is left as it was.  Errors: LBM_ERR_ARG
+ * (null buf, too small), LBM_ERR_STATE (domain resident in a batch),
+ * LBM_ERR_DEVICE. */
+int lbm_save_state(lbm_domain *d, void *buf, size_t bytes);
+
+/* Replace the domain's state with an image written by lbm_save_state.  The
+ * domain must have been created with the same grid, periodic mask, storage
+ * and flags, and must have curved walls exactly when the saved one had;
+ * otherwise LBM_ERR_ARG (a different size, tag or grid) or LBM_ERR_STATE
+ * (other flags, curved walls on one side only, domain resident in a
+ * batch), and the domain is unchanged.  LBM_ERR_DEVICE on a failed copy. */
+int lbm_load_state(lbm_domain *d, const void *buf, size_t bytes);
+
+/*
  * Time statistics (Sec. 2.2, Eqs. (15)-(18): mean velocity and Reynolds
  * stresses; Eq. (19): viscous shear stress, with the strain rate from the
  * second-order Hermite coefficients, App. A, Eqs. (A.7)-(A.8)).  While on,

@@ -72,6 +72,9 @@ SIGNATURES = {
     "lbm_is_wide": (ctypes.c_int, [_vp, _ip]),
     "lbm_get_populations": (ctypes.c_int, [_vp, _fp]),
     "lbm_set_populations": (ctypes.c_int, [_vp, _fp]),
+    "lbm_state_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_save_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "lbm_load_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "lbm_domain_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(DomainInfo)]),
     "lbm_stats_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lbm_stats_get": (ctypes.c_int, [_vp, _dp, _dp, _dp, ctypes.POINTER(ctypes.c_uint64)]),
@@ -237,6 +240,18 @@ class Domain:
     def set_populations(self, f):
         a, p = _f32(f, Q * self.ncells)
         check(lbm_set_populations(self.h, p))
+
+    def save_state(self):
+        """The domain's exact state (lbm_save_state) as a uint8 array."""
+        n = ctypes.c_size_t()
+        check(lbm_state_bytes(self.h, ctypes.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        check(lbm_save_state(self.h, buf.ctypes.data_as(_vp), buf.nbytes))
+        return buf
+
+    def load_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        check(lbm_load_state(self.h, buf.ctypes.data_as(_vp), buf.nbytes))
 
     def stats_enable(self, on=True):
         check(lbm_stats_enable(self.h, 1 if on else 0))

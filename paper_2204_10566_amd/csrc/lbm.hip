@@ -300,6 +300,7 @@ struct lbm_domain {
     std::vector<TileRec> h_tiles; // host copy of the tile list (batch tables are built from it)
     lbm_batch *batch = nullptr;    // resident in this batch
     uint64_t device_bytes = 0;
+    uint64_t flags_hash = 0;       // FNV-1a 64 of the creation flags (state images name it)
 };
 
 namespace {
@@ -668,6 +669,7 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
         return fail(LBM_ERR_ARG, "domain of %llu cells; the limit is 2^32 - 64 cells", (unsigned long long)ncells);
     std::vector<uint64_t> inlet_cells;
     bool outlets = false;
+    uint64_t hash = 0xcbf29ce484222325ull;
     for (uint64_t c = 0; c < ncells; ++c) {
         const uint8_t f = flags[c];
         if (f > LBM_OUTLET)
@@ -678,6 +680,7 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
         if (f == LBM_INLET)
             inlet_cells.push_back(c);
         outlets |= f == LBM_OUTLET;
+        hash = (hash ^ f) * 0x100000001b3ull;
     }
     Tiles T;
     build_tiles(flags, nx, ny, nz, periodic, inlet_cells, outlets, T);
@@ -692,6 +695,7 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     d->P = P;
     d->bytes = bufbytes;
     d->outlets = outlets;
+    d->flags_hash = hash;
     d->ntiles = T.recs.size();
     d->nwall = T.wall.size() / 64;
     d->n_updated = T.n_updated;
@@ -1269,6 +1273,100 @@ int lbm_set_populations(lbm_domain *d, const float *f)
     }
     dfree(d->stream, df);
     return rc;
+}
+
+namespace {
+
+// State images (lbm_save_state): a header of eight uint64 words, then the
+// population array, then the kept curved-wall values.
+constexpr uint64_t kStateTag = 0x31544154534d424cull; // "LBMSTAT1", little-endian
+constexpr size_t kStateHeader = 64;
+
+uint64_t aux_bytes(const lbm_domain *d)
+{
+    return d->d_bzaux ? d->nwall * Q * 64 * sizeof(float) : 0;
+}
+
+void state_header(const lbm_domain *d, uint64_t (&h)[8])
+{
+    h[0] = kStateTag;
+    h[1] = (uint64_t)d->nx | (uint64_t)d->ny << 16 | (uint64_t)d->nz << 32 | (uint64_t)d->periodic << 48 |
+           (uint64_t)d->storage << 56;
+    h[2] = d->bytes;
+    h[3] = aux_bytes(d);
+    h[4] = d->flags_hash;
+    h[5] = (uint64_t)d->phase | (uint64_t)d->unstable << 1;
+    h[6] = h[7] = 0;
+}
+
+} // namespace
+
+int lbm_state_bytes(const lbm_domain *d, size_t *bytes)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!bytes)
+        return fail(LBM_ERR_ARG, "null output");
+    *bytes = kStateHeader + d->bytes + aux_bytes(d);
+    return LBM_OK;
+}
+
+int lbm_save_state(lbm_domain *d, void *buf, size_t bytes)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!buf)
+        return fail(LBM_ERR_ARG, "null buffer");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    const uint64_t aux = aux_bytes(d);
+    if (bytes < kStateHeader + d->bytes + aux)
+        return fail(LBM_ERR_ARG, "buffer of %zu bytes; the state takes %llu", bytes,
+                    (unsigned long long)(kStateHeader + d->bytes + aux));
+    uint64_t h[8];
+    state_header(d, h);
+    std::memcpy(buf, h, sizeof h);
+    char *p = (char *)buf + kStateHeader;
+    if (copy_sync(d->stream, p, d->buf, d->bytes, hipMemcpyDeviceToHost) != hipSuccess ||
+        copy_sync(d->stream, p + d->bytes, d->d_bzaux, aux, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(LBM_ERR_DEVICE, "state download failed");
+    return LBM_OK;
+}
+
+int lbm_load_state(lbm_domain *d, const void *buf, size_t bytes)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (!buf)
+        return fail(LBM_ERR_ARG, "null buffer");
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
+    if (bytes < kStateHeader)
+        return fail(LBM_ERR_ARG, "state image of %zu bytes is shorter than its header", bytes);
+    uint64_t h[8], mine[8];
+    std::memcpy(h, buf, sizeof h);
+    state_header(d, mine);
+    if (h[0] != kStateTag || h[6] != 0 || h[7] != 0 || h[5] > 3)
+        return fail(LBM_ERR_ARG, "not a state image");
+    if (h[1] != mine[1] || h[2] != mine[2])
+        return fail(LBM_ERR_ARG, "state image of another grid, periodicity or storage");
+    if (h[4] != mine[4])
+        return fail(LBM_ERR_STATE, "state image of a domain with other flags");
+    if (h[3] != mine[3])
+        return fail(LBM_ERR_STATE, "state image %s curved walls and the domain %s", h[3] ? "has" : "has no",
+                    mine[3] ? "has" : "has none");
+    if (bytes != kStateHeader + h[2] + h[3])
+        return fail(LBM_ERR_ARG, "state image of %zu bytes; its header gives %llu", bytes,
+                    (unsigned long long)(kStateHeader + h[2] + h[3]));
+    const char *p = (const char *)buf + kStateHeader;
+    if (copy_sync(d->stream, d->buf, p, d->bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        copy_sync(d->stream, d->d_bzaux, p + d->bytes, h[3], hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemsetAsync(d->d_status, 0, sizeof(uint32_t), d->stream) != hipSuccess ||
+        hipStreamSynchronize(d->stream) != hipSuccess)
+        return fail(LBM_ERR_DEVICE, "state upload failed");
+    d->phase = (int)(h[5] & 1u);
+    d->unstable = (h[5] >> 1) != 0;
+    return LBM_OK;
 }
 
 int lbm_stats_enable(lbm_domain *d, int on)

@@ -95,6 +95,10 @@ def test_null_handles(capi):
     assert capi.lbm_destroy(None) == capi.ERR_ARG
     assert capi.lbm_batch_step(None, 1) == capi.ERR_ARG
     assert capi.lbm_batch_destroy(None) == capi.ERR_ARG
+    n = ctypes.c_size_t()
+    assert capi.lbm_state_bytes(None, ctypes.byref(n)) == capi.ERR_ARG
+    assert capi.lbm_save_state(None, None, 0) == capi.ERR_ARG
+    assert capi.lbm_load_state(None, None, 0) == capi.ERR_ARG
 
 
 def test_missing_library_fails_loudly(tmp_path):
