@@ -134,8 +134,8 @@ def copy_ceiling(torch, stream, nbytes, reps=20):
 
 def batched_leg(storage="fp16s"):
     """64 independent periodic / channel domains (edges 16..128, cubes and
-    2:1:1 boxes, tau in [0.51, 0.8]), 500 steps each: packed launches (one
-    per parity class and step) versus one domain after another."""
+    2:1:1 boxes, tau in [0.51, 0.8]), 500 steps each: packed launches
+    (cache-blocked windows of steps) versus one domain after another."""
     from paper_2204_10566_amd import inputs as I
     from paper_2204_10566_amd import serve
 

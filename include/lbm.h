@@ -394,9 +394,8 @@ int lbm_destroy(lbm_domain *d);
 const char *lbm_last_error(void);
 
 /* -------------------------------------------------------------------- */
-/* Batched execution: many independent domains advanced together: one   */
-/* packed launch per parity class and time step, replayed from HIP       */
-/* graphs of up to 8 steps.                                              */
+/* Batched execution: many independent domains advanced together by      */
+/* packed launches replayed from HIP graphs of several steps each.        */
 /* -------------------------------------------------------------------- */
 
 /*
@@ -409,6 +408,21 @@ const char *lbm_last_error(void);
 int lbm_batch_create(size_t hbm_budget_bytes, int storage, void *hip_stream, lbm_batch **out);
 
 /*
+ * Cache blocking of the packed steps.  lbm_batch_step replays graphs of up
+ * to window_steps steps (1..64; default 16).  Within one, the resident
+ * domains run in groups of consecutive domains of one parity class whose
+ * population arrays sum to at most group_bytes (a larger domain is a group
+ * of its own), and each group takes all of the window's steps before the
+ * next group starts, so that a group's populations stay in the device's
+ * last-level cache (256 MB on MI355X) between its steps.  group_bytes 0:
+ * one group per class, each step over every domain before the next step.
+ * Default 192 MiB.  Results do not depend on either setting (domains are
+ * independent); takes effect from the next lbm_batch_step.  Errors:
+ * LBM_ERR_ARG for a window outside 1..64.
+ */
+int lbm_batch_set_cache_block(lbm_batch *b, size_t group_bytes, int window_steps);
+
+/*
  * Admit a domain for n_steps > 0 further steps, starting at the batch's next
  * step.  The domain's state stays where it is (no copy).  The call does not
  * wait for work in flight.  Returns LBM_ERR_OOM when the domain does not fit
@@ -419,8 +433,8 @@ int lbm_batch_create(size_t hbm_budget_bytes, int storage, void *hip_stream, lbm
  */
 int lbm_batch_admit(lbm_batch *b, lbm_domain *d, int n_steps, int *slot);
 
-/* Enqueue n packed steps (asynchronous; one graph replay per up to 8
- * steps).  A resident domain takes part in exactly its admitted number of
+/* Enqueue n packed steps (asynchronous; one graph replay per window of
+ * steps, see lbm_batch_set_cache_block).  A resident domain takes part in exactly its admitted number of
  * steps and ends bit for bit in the state lbm_step would give it alone,
  * whatever it is packed with.  Errors: LBM_ERR_ARG for n < 0. */
 int lbm_batch_step(lbm_batch *b, int n);

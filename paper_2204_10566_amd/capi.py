@@ -82,6 +82,7 @@ SIGNATURES = {
     "lbm_last_error": (ctypes.c_char_p, []),
     "lbm_batch_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "lbm_batch_admit": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _ip]),
+    "lbm_batch_set_cache_block": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int]),
     "lbm_batch_step": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lbm_batch_poll": (ctypes.c_int, [_vp, ctypes.c_int, _ip, ctypes.c_int, _ip]),
     "lbm_batch_release": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
@@ -280,13 +281,16 @@ class Domain:
 
 
 class Batch:
-    """Packed multi-domain execution (one graph-replayed launch per step)."""
+    """Packed multi-domain execution (graph-replayed launches, cache-blocked groups)."""
 
     def __init__(self, budget_bytes, storage="fp16s", stream=None):
         st = STORAGE[storage] if isinstance(storage, str) else int(storage)
         h = _vp()
         check(lbm_batch_create(int(budget_bytes), st, _vp(stream) if stream else None, ctypes.byref(h)))
         self.h = h
+
+    def set_cache_block(self, group_bytes, window_steps=16):
+        check(lbm_batch_set_cache_block(self.h, int(group_bytes), int(window_steps)))
 
     def admit(self, dom: Domain, n_steps: int):
         """Returns the slot id, or None when the budget is exhausted."""

@@ -1328,32 +1328,27 @@ __global__ __launch_bounds__(kBlock) void k_local_collide(KDomain d, const TileR
         local_tile<ST, V, false, W64>(d, tiles[t], lane);
 }
 
-// Packed multi-domain step, one kernel per phase.  ctrl[0] / ctrl[2] =
-// number of tile records of parity class 0 / 1; the kernel runs global
-// step g = ctrl[1] + soff (a graph of several steps gives each of its nodes
-// its offset and advances ctrl[1] once at its end).  The domains of class
-// g mod 2 stream at step g and the others collide locally, so each kernel
-// walks one class's table.  One wave per tile record (the host keeps the
-// grid at least as large as the larger table); each tile belongs to one
-// domain, whose descriptor says whether it takes part in this step.
-// The streaming kernel of the reduced collision without curved walls is
-// bounded to six waves per SIMD: left alone the compiler takes 81 VGPRs
-// (five waves) for FP16S, bounded 72, with no spills (packed steps 0.7 %
-// faster); the curved-wall variants would spill under the same bound.
+// Packed multi-domain step over one range of a tile table (one group of
+// domains of one parity class): the kernel runs global step
+// g = ctrl[1] + soff (a graph of several steps gives each of its nodes its
+// offset and advances ctrl[1] once at its end), and every domain of the
+// range is in the phase PHASE at that step.  One wave per tile record; each
+// tile belongs to one domain, whose descriptor says whether it takes part
+// in this step.  The streaming kernel of the reduced collision without
+// curved walls is bounded to six waves per SIMD: left alone the compiler
+// takes 81 VGPRs (five waves) for FP16S, bounded 72, with no spills (packed
+// steps 0.7 % faster); the curved-wall variants would spill under the same
+// bound.
 template <int V, uint32_t PHASE>
 constexpr int kBatchedMinBlocks = ((V & kVarH1) != 0 && (V & kVarCurved) == 0 && PHASE == 0u) ? 6 : 1;
 
 template <int ST, int V, uint32_t PHASE>
-__global__ __launch_bounds__(kBlock, (kBatchedMinBlocks<V, PHASE>)) void k_collide_batched(const KDomain *__restrict__ doms,
-                                                         const TileRec *__restrict__ tiles0,
-                                                         const TileRec *__restrict__ tiles1,
-                                                         const uint32_t *__restrict__ ctrl, uint32_t soff)
+__global__ __launch_bounds__(kBlock, (kBatchedMinBlocks<V, PHASE>)) void k_collide_batched(
+    const KDomain *__restrict__ doms, const TileRec *__restrict__ tiles, uint32_t ntiles,
+    const uint32_t *__restrict__ ctrl, uint32_t soff)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t g = ctrl[1] + soff;
-    const uint32_t cls = (g & 1u) ^ PHASE;
-    const TileRec *tiles = cls ? tiles1 : tiles0;
-    const uint32_t ntiles = cls ? ctrl[2] : ctrl[0];
     const uint32_t nw = gridDim.x * kWavesPerBlock;
     const uint32_t w0 =
         __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + (threadIdx.x >> 6));

@@ -42,10 +42,19 @@ def small_specs(count, seed, lo=10, hi=26):
     return specs
 
 
+# cache blocks (group bytes, window steps): the default, one group per
+# class, and groups of a few small domains with short and odd windows
+CACHE_BLOCKS = [None, (0, 8), (200_000, 5), (1, 3), (600_000, 1)]
+
+
 @pytest.mark.parametrize("storage", ["fp16s", "fp32"])
-def test_alone_equals_mix_staggered(capi, storage):
+@pytest.mark.parametrize("cache", CACHE_BLOCKS)
+def test_alone_equals_mix_staggered(capi, storage, cache):
+    """Domains admitted at even and odd steps (both parity classes), with
+    different step counts so that some finish inside a window, each end bit
+    for bit where they end alone, whatever the cache blocking."""
     specs = small_specs(6, 1)
-    say(f"alone vs mix {storage}: " + ", ".join(f"{s.kind}{s.nx}x{s.ny}x{s.nz}/{s.steps}" for s in specs))
+    say(f"alone vs mix {storage} cache {cache}: " + ", ".join(f"{s.kind}{s.nx}x{s.ny}x{s.nz}/{s.steps}" for s in specs))
     alone = []
     for s in specs:
         d = build(capi, s, storage)
@@ -54,6 +63,8 @@ def test_alone_equals_mix_staggered(capi, storage):
         d.destroy()
     doms = [build(capi, s, storage) for s in specs]
     b = capi.Batch(1 << 34, storage)
+    if cache:
+        b.set_cache_block(*cache)
     slots = {}
     order = [[0, 1, 2], [3], [4, 5]]
     pending = set()
@@ -101,10 +112,11 @@ def test_budget_limits_admission(capi):
     b.destroy()
 
 
-def test_release_churn_and_compaction(capi):
+@pytest.mark.parametrize("cache", [None, (500_000, 3)])
+def test_release_churn_and_compaction(capi, cache):
     """Admit and release many domains so that the packed table is compacted
     while a long-running domain stays resident; every result still equals
-    its stand-alone run."""
+    its stand-alone run (also with groups of a few domains)."""
     long_spec = I.DomainSpec(kind="tgv", nx=40, ny=40, nz=40, tau=0.62, steps=60).materialise()
     shorts = small_specs(10, 3, lo=30, hi=44)  # ~400-1300 tiles each
     say("churn: one long domain, ten short ones")
@@ -115,6 +127,8 @@ def test_release_churn_and_compaction(capi):
         ref[k] = d.populations()
         d.destroy()
     b = capi.Batch(1 << 34, "fp16s")
+    if cache:
+        b.set_cache_block(*cache)
     long_d = build(capi, long_spec, "fp16s")
     long_slot = b.admit(long_d, long_spec.steps)
     active = {}
@@ -351,7 +365,12 @@ def test_batch_state_errors(capi):
     pops = np.zeros(27 * d.ncells, np.float32).ctypes.data_as(capi._fp)
     n_in = int(d.info().n_inlet)
     uin = np.zeros(max(1, 3 * n_in), np.float32).ctypes.data_as(capi._fp)
+    nimg = ctypes.c_size_t()
+    assert capi.lbm_state_bytes(h, ctypes.byref(nimg)) == 0
+    img = np.zeros(nimg.value, np.uint8)
     state = {
+        "lbm_save_state": capi.lbm_save_state(h, img.ctypes.data_as(capi._vp), img.nbytes),
+        "lbm_load_state": capi.lbm_load_state(h, img.ctypes.data_as(capi._vp), img.nbytes),
         "lbm_step": capi.lbm_step(h, 1),
         "lbm_set_params": capi.lbm_set_params(h, 0.6, 1 / 0.6, 1.0),
         "lbm_set_rates": capi.lbm_set_rates(h, 1.5, 1.5, 1.0),
@@ -372,6 +391,8 @@ def test_batch_state_errors(capi):
     assert capi.lbm_batch_admit(b.h, other.h, 5, ctypes.byref(s)) == capi.ERR_ARG
     assert capi.lbm_batch_admit(b.h, other.h, 0, ctypes.byref(s)) == capi.ERR_ARG
     assert capi.lbm_batch_step(b.h, -1) == capi.ERR_ARG
+    for bad_window in (0, 65):
+        assert capi.lbm_batch_set_cache_block(b.h, 1 << 20, bad_window) == capi.ERR_ARG
     assert capi.lbm_batch_release(b.h, slot, ctypes.byref(dp)) == capi.ERR_STATE
     assert capi.lbm_batch_release(b.h, 999, ctypes.byref(dp)) == capi.ERR_ARG
     assert capi.lbm_batch_destroy(b.h) == capi.ERR_STATE
