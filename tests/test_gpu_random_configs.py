@@ -131,16 +131,19 @@ def build_domain(capi, c, storage):
     return d
 
 
-def test_random_mix_packed_equals_alone(capi):
+@pytest.mark.parametrize("cache", [None, (1, 3), (30_000, 7)])
+def test_random_mix_packed_equals_alone(capi, cache):
     """Eight random configurations packed into one batch (FP16S; reduced and
     general higher-order rates, curved walls, both outlets, ragged and
     row-aligned grids mixed) with different step counts: each ends bit for
-    bit where it ends alone."""
+    bit where it ends alone, with the default cache blocks, with every domain
+    a group of its own over windows of 3 steps, and with groups of a few
+    domains over windows of 7."""
     cases = [make_case(k, "fp16s") for k in range(8)]
     steps = [3 * c["steps"] + k for k, c in enumerate(cases)]
     h1 = [all(v == 1.0 for v in c["order"]) for c in cases]
     assert any(h1) and not all(h1)
-    say(f"packed random mix: steps {steps}, reduced collision {h1}")
+    say(f"packed random mix: steps {steps}, reduced collision {h1}, cache {cache}")
     alone = []
     for c, n in zip(cases, steps):
         d = build_domain(capi, c, "fp16s")
@@ -149,6 +152,8 @@ def test_random_mix_packed_equals_alone(capi):
         d.destroy()
     doms = [build_domain(capi, c, "fp16s") for c in cases]
     b = capi.Batch(1 << 32, "fp16s")
+    if cache:
+        b.set_cache_block(*cache)
     slots = [b.admit(d, n) for d, n in zip(doms, steps)]
     b.step(max(steps))
     assert sorted(b.poll(wait=True)) == sorted(slots)
