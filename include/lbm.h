@@ -263,6 +263,19 @@ int lbm_init_fields(lbm_domain *d, const float *rho, const float *u);
 int lbm_step(lbm_domain *d, int n);
 
 /*
+ * lbm_step in two halves, for callers that overlap host work with the
+ * steps or time them with events on the domain's stream.
+ * lbm_step_async enqueues the n steps on the domain's stream and returns
+ * without waiting; lbm_step_wait waits for all enqueued work and reports
+ * whether any step since the last check went unstable (LBM_ERR_UNSTABLE,
+ * sticky as for lbm_step).  Calls that read or replace the state
+ * synchronise the stream themselves; instability of enqueued steps is
+ * reported by the next lbm_step_wait or lbm_step.  Errors as lbm_step.
+ */
+int lbm_step_async(lbm_domain *d, int n);
+int lbm_step_wait(lbm_domain *d);
+
+/*
  * Build the step graphs now (lbm_step builds them on first use after a
  * change of rates, outlet, walls, statistics or equilibrium order): one
  * graph per run length 64, 32, ..., 2 steps, each a chain of the step

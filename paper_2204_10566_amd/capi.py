@@ -61,6 +61,8 @@ SIGNATURES = {
     "lbm_set_inlet_cells": (ctypes.c_int, [_vp, _fp]),
     "lbm_init_fields": (ctypes.c_int, [_vp, _fp, _fp]),
     "lbm_step": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lbm_step_async": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lbm_step_wait": (ctypes.c_int, [_vp]),
     "lbm_prepare_steps": (ctypes.c_int, [_vp]),
     "lbm_get_moments": (ctypes.c_int, [_vp, _fp, _fp]),
     "lbm_get_moments_device": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -219,6 +221,14 @@ class Domain:
 
     def step_status(self, n=1) -> int:
         return lbm_step(self.h, int(n))
+
+    def step_async(self, n=1):
+        """Enqueue n steps on the domain's stream without waiting."""
+        check(lbm_step_async(self.h, int(n)))
+
+    def wait_status(self) -> int:
+        """Wait for the enqueued steps; their status code (OK or ERR_UNSTABLE)."""
+        return lbm_step_wait(self.h)
 
     def prepare_steps(self):
         """Build the step graphs now (outside a timed run)."""

@@ -1098,7 +1098,7 @@ int lbm_init_fields(lbm_domain *d, const float *rho, const float *u)
     return rc;
 }
 
-int lbm_step(lbm_domain *d, int n)
+int lbm_step_async(lbm_domain *d, int n)
 {
     if (int rc = check_domain(d))
         return rc;
@@ -1136,11 +1136,29 @@ int lbm_step(lbm_domain *d, int n)
     }
     if (d->stats_on)
         d->stats_samples += local_steps;
+    return LBM_OK;
+}
+
+int lbm_step_wait(lbm_domain *d)
+{
+    if (int rc = check_domain(d))
+        return rc;
+    if (d->batch)
+        return fail(LBM_ERR_STATE, "domain is resident in a batch");
     if (int rc = sync_status(d))
         return rc;
     if (d->unstable)
         return fail(LBM_ERR_UNSTABLE, "a step produced rho <= 0 or a non-finite value");
     return LBM_OK;
+}
+
+int lbm_step(lbm_domain *d, int n)
+{
+    if (int rc = lbm_step_async(d, n))
+        return rc;
+    if (d->ntiles == 0) // nothing is updated, the state stays as it is
+        return LBM_OK;
+    return lbm_step_wait(d);
 }
 
 int lbm_prepare_steps(lbm_domain *d)

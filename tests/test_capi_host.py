@@ -100,6 +100,8 @@ def test_null_handles(capi):
     assert capi.lbm_save_state(None, None, 0) == capi.ERR_ARG
     assert capi.lbm_load_state(None, None, 0) == capi.ERR_ARG
     assert capi.lbm_batch_set_cache_block(None, 0, 8) == capi.ERR_ARG
+    assert capi.lbm_step_async(None, 1) == capi.ERR_ARG
+    assert capi.lbm_step_wait(None) == capi.ERR_ARG
 
 
 def test_missing_library_fails_loudly(tmp_path):

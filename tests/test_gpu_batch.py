@@ -372,6 +372,8 @@ def test_batch_state_errors(capi):
         "lbm_save_state": capi.lbm_save_state(h, img.ctypes.data_as(capi._vp), img.nbytes),
         "lbm_load_state": capi.lbm_load_state(h, img.ctypes.data_as(capi._vp), img.nbytes),
         "lbm_step": capi.lbm_step(h, 1),
+        "lbm_step_async": capi.lbm_step_async(h, 1),
+        "lbm_step_wait": capi.lbm_step_wait(h),
         "lbm_set_params": capi.lbm_set_params(h, 0.6, 1 / 0.6, 1.0),
         "lbm_set_rates": capi.lbm_set_rates(h, 1.5, 1.5, 1.0),
         "lbm_set_order_rates": capi.lbm_set_order_rates(h, 1.0, 1.0, 1.0, 1.0),

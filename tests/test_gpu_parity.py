@@ -351,6 +351,36 @@ def test_unstable_run_reports_error(capi):
     assert d.step_status(3) == capi.OK
 
 
+def test_async_steps_equal_synchronous_steps(capi):
+    """lbm_step_async followed by lbm_step_wait gives the same bits as
+    lbm_step, across graph replays and odd counts, and the wait reports an
+    unstable step as lbm_step does."""
+    say("async steps")
+    fl = I.periodic_box(12)
+    u0 = I.taylor_green_velocity(12, 12, 12, 0.04).astype(np.float32)
+    out = []
+    for use_async in (False, True):
+        d = capi.Domain(fl, periodic=7)
+        d.set_params(0.57)
+        d.init_fields(None, u0)
+        for n in (1, 70, 3, 0, 129):
+            if use_async:
+                d.step_async(n)
+                assert d.wait_status() == capi.OK
+            else:
+                d.step(n)
+        out.append(d.populations())
+        d.destroy()
+    assert np.array_equal(out[0], out[1])
+    d = capi.Domain(fl, periodic=7)
+    d.set_params(0.6)
+    d.set_populations(-np.ones((27,) + fl.shape, np.float32) * 0.01)
+    d.step_async(2)
+    assert d.wait_status() == capi.ERR_UNSTABLE
+    assert d.step_status(1) == capi.ERR_UNSTABLE
+    d.destroy()
+
+
 def test_adopted_torch_array_and_stream(capi, orc):
     """The population array and the stream come from torch."""
     import torch
