@@ -751,6 +751,12 @@ int create(const uint8_t *flags, int nx, int ny, int nz, unsigned periodic, int 
     if (build_inlet_terms(d) != hipSuccess)
         return bail(fail(LBM_ERR_DEVICE, "inlet terms"));
     d->omega = d->omega_b = 1.0 / 0.6;
+    // the side rows' elements that no outlet cell uses, and the padding
+    // after them, are never written: zero, so that state images are
+    // deterministic (the tile blocks are written by init_eq)
+    const uint64_t tile_bytes = (uint64_t)Q * P * storage_bytes(storage);
+    if (hipMemsetAsync(d->buf + tile_bytes, 0, bufbytes - tile_bytes, d->stream) != hipSuccess)
+        return bail(fail(LBM_ERR_DEVICE, "side rows"));
     int rc = init_eq(d, nullptr, nullptr);
     if (rc == LBM_OK && hipStreamSynchronize(d->stream) != hipSuccess)
         rc = fail(LBM_ERR_DEVICE, "initialisation failed");
@@ -1012,6 +1018,9 @@ int lbm_set_wall_distances(lbm_domain *d, const float *q)
                           hipMemcpyHostToDevice));
     if (any) {
         HIP_TRY(copy_sync(d->stream, d->d_bzc, coef.data(), nco * sizeof(float2), hipMemcpyHostToDevice));
+        // kept values of lanes and links without a curved coefficient are
+        // never written: zero, so that state images are deterministic
+        HIP_TRY(hipMemsetAsync(d->d_bzaux, 0, nco * sizeof(float), d->stream));
         HIP_TRY(curved_refresh(d));
         HIP_TRY(hipStreamSynchronize(d->stream));
     }

@@ -147,3 +147,59 @@ def test_state_image_rejections(capi):
     assert np.array_equal(same.populations(), before)
     same.load_state(image)
     same.destroy()
+
+
+def fnv1a64(data: bytes) -> int:
+    h = 0xCBF29CE484222325
+    for b in data:
+        h = ((h ^ b) * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_state_image_layout(capi):
+    """The image's header holds what the header file documents: the tag, the
+    grid, periodicity and storage, the array and kept-value sizes, the FNV-1a
+    hash of the flags, the phase and instability flag; the array follows."""
+    c = make_case(701)  # curved walls, pressure outlet
+    for storage in ("fp32", "fp16s"):
+        d = build_domain(capi, c, storage)
+        d.step(5)  # odd: the image keeps phase 1
+        img = d.save_state()
+        nz, ny, nx = c["fl"].shape
+        h = np.frombuffer(img[:64].tobytes(), "<u8")
+        st = capi.STORAGE[storage]
+        assert h[0] == int.from_bytes(b"LBMSTAT1", "little")
+        assert h[1] == nx | ny << 16 | nz << 32 | c["periodic"] << 48 | st << 56
+        assert h[2] == capi.lbm_array_bytes(nx, ny, nz, st)
+        assert h[3] == d.info().n_wall_tiles * 27 * 64 * 4
+        assert h[4] == fnv1a64(np.ascontiguousarray(c["fl"]).tobytes())
+        assert h[5] == 1 and h[6] == 0 and h[7] == 0
+        assert img.nbytes == 64 + int(h[2]) + int(h[3])
+        d.destroy()
+
+
+def test_state_image_between_addressing_modes(capi):
+    """An image taken with the 64-bit addressing kernels restarts under the
+    32-bit ones (and back) bit for bit: the image is the array as stored,
+    whichever kernels stepped it."""
+    c = make_case(706)
+    for storage in ("fp32", "bf16s"):
+        d = build_domain(capi, c, storage)
+        d.step(9)
+        ref_img = d.save_state()
+        d.step(6)
+        ref = d.populations()
+        d.destroy()
+        for wide_first in (True, False):
+            d = build_domain(capi, c, storage)
+            d.debug_wide_addressing(wide_first)
+            d.step(9)
+            img = d.save_state()
+            assert np.array_equal(img, ref_img)
+            d.destroy()
+            r = build_domain(capi, c, storage)
+            r.debug_wide_addressing(not wide_first)
+            r.load_state(img)
+            r.step(6)
+            assert np.array_equal(r.populations(), ref)
+            r.destroy()
