@@ -423,12 +423,14 @@ int lbm_batch_create(size_t hbm_budget_bytes, int storage, void *hip_stream, lbm
 /*
  * Cache blocking of the packed steps.  lbm_batch_step replays graphs of up
  * to window_steps steps (1..64; default 16).  Within one, the resident
- * domains run in groups of consecutive domains of one parity class whose
- * population arrays sum to at most group_bytes (a larger domain is a group
- * of its own), and each group takes all of the window's steps before the
- * next group starts, so that a group's populations stay in the device's
- * last-level cache (256 MB on MI355X) between its steps.  group_bytes 0:
- * one group per class, each step over every domain before the next step.
+ * domains run in groups of consecutive domains of one parity class and one
+ * addressing kind (row-aligned or not) whose tile blocks (27 * 64
+ * populations per tile) sum to at most group_bytes (a larger domain is a
+ * group of its own), and each group takes all of the window's steps before
+ * the next group starts, so that a group's populations stay in the
+ * device's last-level cache (256 MB on MI355X) between its steps.
+ * group_bytes 0: no limit (one group per class and kind, each step over
+ * every domain before the next step).
  * Default 192 MiB.  Results do not depend on either setting (domains are
  * independent); takes effect from the next lbm_batch_step.  Errors:
  * LBM_ERR_ARG for a window outside 1..64.

@@ -26,10 +26,12 @@
     PREFIX __global__ void k_stream_collide<ST, V, true, false>(KDomain, const TileRec *, uint32_t);          \
     PREFIX __global__ void k_stream_collide<ST, V, false, false>(KDomain, const TileRec *, uint32_t);         \
     PREFIX __global__ void k_local_collide<ST, V, false>(KDomain, const TileRec *, uint32_t);                 \
-    PREFIX __global__ void k_collide_batched<ST, V, 0u>(const KDomain *, const TileRec *, uint32_t,             \
-                                                        const uint32_t *, uint32_t);                            \
-    PREFIX __global__ void k_collide_batched<ST, V, 1u>(const KDomain *, const TileRec *, uint32_t,             \
-                                                        const uint32_t *, uint32_t);
+    PREFIX __global__ void k_collide_batched<ST, V, 0u, false>(const KDomain *, const TileRec *, uint32_t,      \
+                                                               const uint32_t *, uint32_t);                     \
+    PREFIX __global__ void k_collide_batched<ST, V, 0u, true>(const KDomain *, const TileRec *, uint32_t,       \
+                                                              const uint32_t *, uint32_t);                      \
+    PREFIX __global__ void k_collide_batched<ST, V, 1u, false>(const KDomain *, const TileRec *, uint32_t,      \
+                                                               const uint32_t *, uint32_t);
 
 #define LBM_INST_WIDE_VARIANT(PREFIX, ST, V)                                                                   \
     PREFIX __global__ void k_stream_collide<ST, V, true, true>(KDomain, const TileRec *, uint32_t);           \
