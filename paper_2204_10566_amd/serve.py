@@ -131,7 +131,7 @@ def summarise(mode, outs, wall, budget=None):
 DEFAULT_WORK_CAP_CELLS = 3_000_000
 
 
-def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=8, max_ahead=2, workers=4,
+def serve_continuous(trace, storage="fp16s", budget_bytes=None, steps_per_tick=16, max_ahead=2, workers=4,
                      keep_fields=False, realtime=True, work_cap_cells=DEFAULT_WORK_CAP_CELLS, order="fifo"):
     """Serve a trace with continuous batching.  Returns (outcomes, summary).
 
